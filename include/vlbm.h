@@ -1,0 +1,147 @@
+/*
+ * vlbm.h -- C ABI of the MI355X (gfx950) vielbein lattice Boltzmann library.
+ *
+ * The library advances the D2Q16 populations f_k(theta, phi) of the vielbein
+ * lattice Boltzmann method on a sphere (arXiv:2504.15574, Sec. III): BGK
+ * collision toward the order-3 Hermite equilibrium, the Hermite-projected
+ * inertial force, WENO-5 flux-form advection in theta and phi with periodic and
+ * pole ghosts, and SSP-RK3 time stepping (Sec. III.G, eq. (Lf)).
+ *
+ * Conventions shared by every entry point
+ *  - Grid (Sec. III.D, eq. (discrete_coord_sphere), 0-based): theta_s =
+ *    (s + 1/2) pi / n_theta, phi_q = (q + 1/2) 2 pi / n_phi.
+ *  - Fields are FP64, row-major [n_theta][n_phi] (phi fastest).  Velocities are
+ *    the orthonormal (vielbein) components u^theta, u^phi.
+ *  - Populations exchanged through the ABI are FP64 [16][n_theta][n_phi] with
+ *    k = 4*k_theta + k_phi over the ascending nodes -sqrt(3+sqrt6),
+ *    -sqrt(3-sqrt6), +sqrt(3-sqrt6), +sqrt(3+sqrt6) (App. A.2).
+ *  - "ptr_on_device" = 1: the pointer is HIP device memory and the call is
+ *    asynchronous on the context stream; 0: host memory and the call
+ *    synchronises the context stream before returning.
+ *  - Every function returns a vlbm_status; no C++ exception crosses the ABI.
+ *    On failure vlbm_last_error() (thread-local) describes the cause.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Memory: the caller owns the device workspace (size from
+ *    vlbm_workspace_bytes) and every field buffer; the library owns only the
+ *    context object.  The workspace must outlive the context.
+ */
+#ifndef VLBM_H
+#define VLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VLBM_ABI_VERSION 1u
+
+typedef struct vlbm_ctx vlbm_ctx;
+
+typedef enum {
+    VLBM_OK = 0,
+    VLBM_ERR_ARG = 1,          /* invalid argument; nothing was changed        */
+    VLBM_ERR_UNSUPPORTED = 2,  /* valid but not implemented (Q != 4, scheme)   */
+    VLBM_ERR_ALLOC = 3,        /* workspace too small / host allocation failed */
+    VLBM_ERR_DEVICE = 4,       /* a HIP call failed                            */
+    VLBM_ERR_UNSTABLE = 5      /* diagnostics found non-finite populations     */
+} vlbm_status;
+
+typedef enum {
+    VLBM_STORE_F64 = 0,      /* f_k - w_k rho0 stored in FP64, FP64 arithmetic          */
+    VLBM_STORE_F32_DEV = 1,  /* f_k - w_k rho0 stored in FP32, FP32 arithmetic          */
+    VLBM_STORE_F16_DEV = 2   /* (f_k - w_k rho0) * 2^e_k stored in FP16, FP32 arithmetic */
+} vlbm_storage;
+
+typedef enum {
+    VLBM_ADV_WENO5 = 0       /* WENO-5 fluxes, eqs. (fluxes_W5)-(WENO5_sigma) */
+} vlbm_advection;
+
+/* Problem statement (Sec. III, Sec. IV): grid, quadrature, tau, dt, scheme. */
+typedef struct {
+    uint32_t abi_version;  /* must equal VLBM_ABI_VERSION                            */
+    int32_t n_theta;       /* >= 3 (pole ghosts mirror rows 0..2)                    */
+    int32_t n_phi;         /* 1 (axisymmetric) or even (phi + pi must be a column)   */
+    int32_t q;             /* Gauss-Hermite points per axis; only 4 is implemented   */
+    double radius;         /* R > 0                                                  */
+    double tau;            /* BGK relaxation time > 0 (nu = tau at T0 = 1)           */
+    double dt;             /* time step > 0; not clamped (see vlbm_suggest_dt)       */
+    double rho0;           /* reference density of the stored deviations (> 0)       */
+    double weno_eps;       /* > 0; nonlinear weights delta_j / (eps + sigma_j)^2     */
+    int32_t storage;       /* vlbm_storage                                           */
+    int32_t advection;     /* vlbm_advection                                         */
+} vlbm_params;
+
+/* Bytes of device workspace a context with these parameters needs (0 when the
+ * parameters are invalid).  Holds the three population buffers of SSP-RK3
+ * (f_n and two stages), FP64 metric tables, FP64 field staging and reduction
+ * partials. */
+size_t vlbm_workspace_bytes(const vlbm_params* params);
+
+/* Create a context on the current HIP device.  hip_stream: a hipStream_t (NULL:
+ * the default stream) on which every kernel of the context is launched.
+ * workspace: device memory of at least vlbm_workspace_bytes(params) bytes,
+ * 256-byte aligned.  Builds the FP64 tables (nodes, weights, K^H and K~^H of
+ * eqs. (kernels), sin/cot tables of Sec. III.E) and uploads them; synchronises
+ * the stream once.  Errors: VLBM_ERR_ARG (bad params / NULL pointers),
+ * VLBM_ERR_UNSUPPORTED (q != 4, unknown storage or scheme), VLBM_ERR_ALLOC
+ * (workspace too small), VLBM_ERR_DEVICE. */
+vlbm_status vlbm_create(const vlbm_params* params, void* hip_stream, void* workspace,
+                        size_t workspace_bytes, vlbm_ctx** out);
+
+/* Set f_n = f^eq(rho, u, T) cell by cell (order-3 Hermite projection of a
+ * Maxwellian at temperature T; T NULL means T = 1 everywhere), then encode it
+ * in the storage format.  Fields as described above. */
+vlbm_status vlbm_init_fields(vlbm_ctx* ctx, const double* rho, const double* u_theta,
+                             const double* u_phi, const double* T, int ptr_on_device);
+
+/* Advance n_steps >= 0 SSP-RK3 steps (Sec. III.G): three fused stage kernels per
+ * step on the context stream, asynchronous.  Validates only its arguments. */
+vlbm_status vlbm_step(vlbm_ctx* ctx, int64_t n_steps);
+
+/* Macroscopic fields (eq. (f_moments_sum)): rho = sum f, u = sum f v / rho and
+ * T = sum f |v - u|^2 / (2 rho).  T may be NULL. */
+vlbm_status vlbm_moments(vlbm_ctx* ctx, double* rho, double* u_theta, double* u_phi,
+                         double* T, int ptr_on_device);
+
+/* Release the context (not the workspace, which belongs to the caller). */
+vlbm_status vlbm_destroy(vlbm_ctx* ctx);
+
+/* ---- support entry points (tests, checkpoints, diagnostics) ---- */
+
+/* FP64 global reductions over the sphere with area element R^2 sin th dth dph:
+ * out[0] mass, out[1] sum f|v|^2/2, out[2] kinetic energy rho|u|^2/2,
+ * out[3] angular momentum rho u_phi R sin th, out[4] count of non-finite
+ * populations, out[5] max |u|, out[6] min rho, out[7] max rho.  Host output;
+ * synchronises the stream.  Returns VLBM_ERR_UNSTABLE when out[4] > 0. */
+vlbm_status vlbm_diagnostics(vlbm_ctx* ctx, double out[8]);
+
+/* Vorticity [d_th(u_phi sin th) - d_ph u_th] / (R sin th) (Sec. IV.D) of the
+ * current state, fourth-order central differences, pole continuation by
+ * velocity inversion at phi + pi.  Output field as above. */
+vlbm_status vlbm_vorticity(vlbm_ctx* ctx, double* omega, int ptr_on_device);
+
+/* Decode the current populations f_n to FP64 [16][n_theta][n_phi]. */
+vlbm_status vlbm_get_populations(vlbm_ctx* ctx, double* f, int ptr_on_device);
+
+/* Encode FP64 populations [16][n_theta][n_phi] into f_n (checkpoint resume). */
+vlbm_status vlbm_set_populations(vlbm_ctx* ctx, const double* f, int ptr_on_device);
+
+/* Largest stable time step suggested for these parameters: the smallest of
+ * 0.2 dth, tau (explicit BGK needs dt < tau, Sec. V) and half the phi-CFL limit
+ * of the row next to the pole, 0.5 R sin(dth/2) dph / v_max (dropped when
+ * n_phi = 1).  Returns 0 for invalid parameters. */
+double vlbm_suggest_dt(const vlbm_params* params);
+
+/* Number of stage-kernel launches issued so far by this context. */
+int64_t vlbm_stage_launches(const vlbm_ctx* ctx);
+
+/* Text of the last error on this thread ("" if none). */
+const char* vlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLBM_H */

@@ -1,0 +1,235 @@
+"""Thin ctypes binding of ``libvlbm.so`` (the C ABI declared in include/vlbm.h).
+
+The functions below carry the C names and only marshal arguments; every step
+of the update runs in the library's HIP kernels.  ``Solver`` adds the one
+convenience the ABI leaves to the caller: device memory for the workspace and
+the stream, both taken from PyTorch (``torch.cuda``).  There is no CPU
+fallback: without the built library or a HIP device the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvlbm.so")
+
+ABI_VERSION = 1
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_ALLOC", 4: "ERR_DEVICE",
+          5: "ERR_UNSTABLE"}
+ADV_WENO5 = 0
+
+# (name, restype, argtypes) of every symbol include/vlbm.h declares
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class vlbm_params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32),
+        ("n_theta", ctypes.c_int32),
+        ("n_phi", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("radius", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+        ("storage", ctypes.c_int32),
+        ("advection", ctypes.c_int32),
+    ]
+
+
+_P = ctypes.POINTER(vlbm_params)
+SIGNATURES = [
+    ("vlbm_workspace_bytes", ctypes.c_size_t, [_P]),
+    ("vlbm_create", ctypes.c_int, [_P, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    ("vlbm_init_fields", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int]),
+    ("vlbm_step", ctypes.c_int, [_vp, ctypes.c_int64]),
+    ("vlbm_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int]),
+    ("vlbm_destroy", ctypes.c_int, [_vp]),
+    ("vlbm_diagnostics", ctypes.c_int, [_vp, _dp]),
+    ("vlbm_vorticity", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    ("vlbm_get_populations", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    ("vlbm_set_populations", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    ("vlbm_suggest_dt", ctypes.c_double, [_P]),
+    ("vlbm_stage_launches", ctypes.c_int64, [_vp]),
+    ("vlbm_last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+class VlbmError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise VlbmError(f"{path} is missing: build it with paper_2504_15574_amd/build.py")
+        L = ctypes.CDLL(path)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        msg = load().vlbm_last_error().decode(errors="replace")
+        raise VlbmError(f"{what}: {STATUS.get(st, st)}: {msg}")
+
+
+def make_params(n_theta, n_phi, tau, dt, storage="f64", radius=1.0, rho0=1.0, weno_eps=1e-6,
+                q=4) -> vlbm_params:
+    return vlbm_params(ABI_VERSION, int(n_theta), int(n_phi), int(q), float(radius), float(tau),
+                       float(dt), float(rho0), float(weno_eps), STORAGE[storage], ADV_WENO5)
+
+
+# ---- C-named wrappers (argument marshalling only) -------------------------------
+def vlbm_workspace_bytes(p: vlbm_params) -> int:
+    return int(load().vlbm_workspace_bytes(ctypes.byref(p)))
+
+
+def vlbm_suggest_dt(p: vlbm_params) -> float:
+    return float(load().vlbm_suggest_dt(ctypes.byref(p)))
+
+
+def vlbm_create(p: vlbm_params, stream: int, workspace: int, nbytes: int) -> int:
+    out = _vp()
+    _check(load().vlbm_create(ctypes.byref(p), _vp(stream), _vp(workspace), nbytes,
+                              ctypes.byref(out)), "vlbm_create")
+    return out.value
+
+
+def vlbm_init_fields(ctx, rho, ut, up, T, on_device: int):
+    _check(load().vlbm_init_fields(_vp(ctx), _vp(rho), _vp(ut), _vp(up), _vp(T), on_device),
+           "vlbm_init_fields")
+
+
+def vlbm_step(ctx, n: int):
+    _check(load().vlbm_step(_vp(ctx), int(n)), "vlbm_step")
+
+
+def vlbm_moments(ctx, rho, ut, up, T, on_device: int):
+    _check(load().vlbm_moments(_vp(ctx), _vp(rho), _vp(ut), _vp(up), _vp(T), on_device),
+           "vlbm_moments")
+
+
+def vlbm_destroy(ctx):
+    _check(load().vlbm_destroy(_vp(ctx)), "vlbm_destroy")
+
+
+def vlbm_diagnostics(ctx, raise_unstable: bool = True) -> np.ndarray:
+    out = np.zeros(8)
+    st = load().vlbm_diagnostics(_vp(ctx), out.ctypes.data_as(_dp))
+    if st == 5 and not raise_unstable:
+        return out
+    _check(st, "vlbm_diagnostics")
+    return out
+
+
+def vlbm_vorticity(ctx, om, on_device: int):
+    _check(load().vlbm_vorticity(_vp(ctx), _vp(om), on_device), "vlbm_vorticity")
+
+
+def vlbm_get_populations(ctx, f, on_device: int):
+    _check(load().vlbm_get_populations(_vp(ctx), _vp(f), on_device), "vlbm_get_populations")
+
+
+def vlbm_set_populations(ctx, f, on_device: int):
+    _check(load().vlbm_set_populations(_vp(ctx), _vp(f), on_device), "vlbm_set_populations")
+
+
+def vlbm_stage_launches(ctx) -> int:
+    return int(load().vlbm_stage_launches(_vp(ctx)))
+
+
+# ---- convenience object ---------------------------------------------------------
+def _host(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data
+
+
+class Solver:
+    """One vLBM run on the current HIP device.
+
+    Workspace: a ``torch.uint8`` device tensor owned by this object; stream:
+    ``torch.cuda.current_stream()`` at construction (or ``stream``)."""
+
+    def __init__(self, n_theta, n_phi, tau, dt=None, storage="f64", radius=1.0, rho0=1.0,
+                 weno_eps=1e-6, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise VlbmError("no HIP device visible to torch")
+        load()
+        self.n_theta, self.n_phi = int(n_theta), int(n_phi)
+        p = make_params(n_theta, n_phi, tau, 1.0, storage, radius, rho0, weno_eps)
+        if dt is None:
+            dt = vlbm_suggest_dt(p)
+        p.dt = float(dt)
+        self.params = p
+        self.dt = float(dt)
+        nbytes = vlbm_workspace_bytes(p)
+        if nbytes == 0:
+            raise VlbmError("invalid parameters: " + load().vlbm_last_error().decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ctx = vlbm_create(p, self.stream.cuda_stream, self.workspace.data_ptr(), nbytes)
+        self.t = 0.0
+
+    # fields: numpy (host) arrays [n_theta, n_phi]
+    def init_fields(self, rho, ut, up, T=None):
+        shape = (self.n_theta, self.n_phi)
+        arrs = [_host(np.broadcast_to(a, shape)) for a in (rho, ut, up)]
+        Ta = _host(np.broadcast_to(T, shape)) if T is not None else (None, None)
+        vlbm_init_fields(self.ctx, arrs[0][1], arrs[1][1], arrs[2][1], Ta[1], 0)
+        self.t = 0.0
+
+    def step(self, n=1):
+        vlbm_step(self.ctx, n)
+        self.t += n * self.dt
+
+    def moments(self, with_T=True):
+        shape = (self.n_theta, self.n_phi)
+        out = [np.empty(shape) for _ in range(4 if with_T else 3)]
+        vlbm_moments(self.ctx, out[0].ctypes.data, out[1].ctypes.data, out[2].ctypes.data,
+                     out[3].ctypes.data if with_T else None, 0)
+        return tuple(out)
+
+    def vorticity(self):
+        om = np.empty((self.n_theta, self.n_phi))
+        vlbm_vorticity(self.ctx, om.ctypes.data, 0)
+        return om
+
+    def populations(self):
+        f = np.empty((16, self.n_theta, self.n_phi))
+        vlbm_get_populations(self.ctx, f.ctypes.data, 0)
+        return f
+
+    def set_populations(self, f):
+        f, ptr = _host(f)
+        assert f.shape == (16, self.n_theta, self.n_phi)
+        vlbm_set_populations(self.ctx, ptr, 0)
+
+    def diagnostics(self, raise_unstable=True):
+        return vlbm_diagnostics(self.ctx, raise_unstable)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            vlbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,204 @@
+"""GPU (HIP) path vs the CPU FP64 oracle, through the C ABI.
+
+Element-by-element comparisons on seeded inputs at sizes the oracle finishes
+in seconds, spanning several 4 x 64 tiles with ragged tails in theta and phi,
+the axisymmetric (n_phi = 1) case and the pole rows.  FP64 storage must agree
+with the oracle to 1e-12 relative (max-abs over all populations, scaled by
+max |f|); the reduced-precision formats report their error as a number and
+are held to bounds derived from their unit round-off.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    from paper_2504_15574_amd import load
+    load()
+
+
+def _solver(nt, nph, tau, dt, storage="f64", **kw):
+    from paper_2504_15574_amd import Solver
+    return Solver(nt, nph, tau, dt, storage=storage, **kw)
+
+
+V, W1 = oracle.quadrature()
+WK = np.outer(W1, W1).reshape(16)
+
+
+def _errs(fg, fr, rho0=1.0):
+    dev = fr - WK[:, None, None] * rho0
+    ad = np.abs(fg - fr).max()
+    return ad / np.abs(fr).max(), ad / max(np.abs(dev).max(), 1e-300)
+
+
+def _run_both(state, nt, nph, tau, dt, n, storage="f64", R=1.0):
+    rho, ut, up, T = state
+    print(f"[case] {storage} {nt}x{nph} tau={tau} dt={dt} steps={n}", flush=True)
+    s = _solver(nt, nph, tau, dt, storage, radius=R)
+    s.init_fields(rho, ut, up, T)
+    s.step(n)
+    fg = s.populations()
+    s.close()
+    fr = oracle.step(oracle.init(rho, ut, up, T), n, R=R, tau=tau, dt=dt, threads=THREADS)
+    return fg, fr
+
+
+def test_init_matches_oracle_equilibrium():
+    st = W.random_state(20, 34, seed=3, du=0.1, dT=0.1)
+    s = _solver(20, 34, 1e-3, 1e-4)
+    s.init_fields(*st)
+    fg = s.populations()
+    fr = oracle.init(*st)
+    assert np.abs(fg - fr).max() < 1e-15
+    r, a, b, T = s.moments()
+    rr, ar, br, Tr = oracle.moments(fr)
+    assert np.abs(r - rr).max() < 1e-14
+    assert np.abs(a - ar).max() < 1e-14 and np.abs(b - br).max() < 1e-14
+    assert np.abs(T - Tr).max() < 1e-13
+    # the thermal initial state reproduces its own T (order-3 Hermite projection)
+    assert np.abs(T - st[3]).max() < 1e-13
+
+
+@pytest.mark.parametrize("nt,nph,seed,smooth", [
+    (26, 50, 1, False),      # ragged in theta (26 = 6*4 + 2) and phi (50 < 64)
+    (22, 192, 2, True),      # three phi tiles
+    (37, 1, 3, False),       # axisymmetric, odd n_theta
+    (8, 130, 4, False),      # two full tiles + a 2-column tail; every row is a pole row
+])
+def test_f64_parity_random_states(nt, nph, seed, smooth):
+    st = W.random_state(nt, nph, seed=seed, du=0.05, dT=0.05, smooth=smooth)
+    tau = 2e-3
+    dt = oracle.suggest_dt(nt, nph, tau)
+    fg, fr = _run_both(st, nt, nph, tau, dt, 12)
+    rel, reldev = _errs(fg, fr)
+    print(f"  max rel {rel:.2e}  (vs deviation scale {reldev:.2e})")
+    assert rel <= 1e-12
+
+
+def test_f64_parity_c1_sound_wave_full():
+    # C1: 32 x 64, nu = tau = 1e-3, dt = 1e-3, 500 steps, rho = 1 + 1e-3 P2(cos th)
+    st = W.sound_wave_p2(32, 64)
+    fg, fr = _run_both(st, 32, 64, 1e-3, 1e-3, 500)
+    rel, reldev = _errs(fg, fr)
+    print(f"  C1 max rel {rel:.2e} (deviation-relative {reldev:.2e})")
+    assert rel <= 1e-12
+    # phi-uniform data stay bitwise phi-uniform on the GPU too
+    assert np.array_equal(fg, np.repeat(fg[:, :, :1], 64, axis=2))
+
+
+def test_f64_parity_random_vorticity_2d():
+    # C2-type state (shear wave + random toroidal vorticity, l <= 16) at 64 x 128
+    st = W.random_vorticity_state(64, 128, seed=0, lmax=16, amp=1e-2, shear=1e-2)
+    tau = 5e-4
+    dt = oracle.suggest_dt(64, 128, tau)
+    fg, fr = _run_both(st, 64, 128, tau, dt, 50)
+    rel, reldev = _errs(fg, fr)
+    print(f"  C2-type max rel {rel:.2e} (deviation-relative {reldev:.2e})")
+    assert rel <= 1e-12
+
+
+def test_f64_radius_and_rho0():
+    st = W.random_state(16, 64, seed=9, drho=0.1, du=0.05)
+    rho, ut, up, T = st
+    rho = rho * 1.7
+    s = _solver(16, 64, 3e-3, 1e-3, "f64", radius=2.5, rho0=1.7)
+    s.init_fields(rho, ut, up)
+    s.step(10)
+    fg = s.populations()
+    s.close()
+    fr = oracle.step(oracle.init(rho, ut, up), 10, R=2.5, tau=3e-3, dt=1e-3, threads=THREADS)
+    assert _errs(fg, fr, 1.7)[0] <= 1e-12
+
+
+def test_stage_launch_count_and_determinism():
+    st = W.random_state(24, 96, seed=5, du=0.05, smooth=False)
+    outs = []
+    for _ in range(2):
+        s = _solver(24, 96, 2e-3, 5e-4)
+        s.init_fields(*st)
+        s.step(7)
+        from paper_2504_15574_amd import vlbm_stage_launches
+        assert vlbm_stage_launches(s.ctx) == 21
+        outs.append(s.populations())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])    # no LDS race: bitwise repeatable
+
+
+def test_checkpoint_resume_continues_the_run():
+    st = W.random_state(16, 64, seed=6, du=0.05)
+    a = _solver(16, 64, 2e-3, 5e-4)
+    a.init_fields(*st)
+    a.step(20)
+    straight = a.populations()
+    b = _solver(16, 64, 2e-3, 5e-4)
+    b.init_fields(*st)
+    b.step(10)
+    ck = b.populations()
+    c = _solver(16, 64, 2e-3, 5e-4)
+    c.set_populations(ck)
+    c.step(10)
+    resumed = c.populations()
+    for x in (a, b, c):
+        x.close()
+    assert np.abs(resumed - straight).max() < 1e-15
+
+
+def test_diagnostics_and_vorticity_match_oracle():
+    st = W.random_vorticity_state(48, 96, seed=2, lmax=8, amp=1e-2, shear=1e-2)
+    s = _solver(48, 96, 1e-3, 1e-4, radius=1.3)
+    s.init_fields(*st)
+    s.step(3)
+    d = s.diagnostics()
+    om = s.vorticity()
+    f = s.populations()
+    r, a, b, T = s.moments()
+    s.close()
+    dr = oracle.diagnostics(f, 1.3)
+    assert np.allclose(d[[0, 1, 2, 3]], dr[[0, 1, 2, 3]], rtol=1e-12, atol=1e-18)
+    assert d[4] == 0 and dr[4] == 0
+    assert np.allclose(d[5:], dr[5:], rtol=1e-13)
+    omr = oracle.vorticity(a, b, 1.3)
+    assert np.abs(om - omr).max() <= 1e-12 * np.abs(omr).max()
+
+
+def test_unstable_run_is_detected():
+    # dt = 4 tau exceeds the SSP-RK3 stability limit of the stiff BGK term
+    # (|dt/tau| < 2.51 on the negative real axis): the run blows up and the
+    # diagnostics report non-finite populations instead of silently continuing.
+    st = W.random_state(16, 32, seed=7, du=0.05, smooth=False)
+    s = _solver(16, 32, 1e-3, 4e-3)
+    s.init_fields(*st)
+    s.step(400)
+    d = s.diagnostics(raise_unstable=False)
+    from paper_2504_15574_amd import VlbmError
+    with pytest.raises(VlbmError):
+        s.diagnostics()
+    s.close()
+    assert d[4] > 0
+
+
+@pytest.mark.parametrize("storage,bound", [("f32", 2e-5), ("f16", 5e-3)])
+def test_reduced_precision_error_vs_oracle(storage, bound):
+    # Deviation storage: the error is reported relative to the deviation scale
+    # max |f - w rho0| (the part of f that carries the flow).
+    st = W.random_vorticity_state(64, 128, seed=1, lmax=12, amp=2e-2, shear=2e-2)
+    tau = 5e-4
+    dt = oracle.suggest_dt(64, 128, tau)
+    fg, fr = _run_both(st, 64, 128, tau, dt, 30, storage)
+    rel, reldev = _errs(fg, fr)
+    print(f"  {storage}: max rel {rel:.2e}, deviation-relative {reldev:.2e}")
+    assert reldev < bound
