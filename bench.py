@@ -1,0 +1,230 @@
+"""Throughput benchmark of the vLBM step on one MI355X.
+
+Workload: decaying 2-D turbulence on the sphere, 2048 x 4096 cells, D2Q16
+(Q = 16 populations), nu = tau = 1e-5, dt from the stability rule (2.52e-7),
+seeded streamfunction with E(l) ~ l^-3 over l = 1..256 normalised to an rms
+|u| of 0.05 (synthetic data).  A step is one full SSP-RK3 update (three fused
+stage kernels) of all 16 populations on every cell; MLUPS = cells * steps /
+seconds / 1e6, with the populations resident in HBM.
+
+The headline ``value`` is the FP32-deviation-store MLUPS; the FP64 and FP16
+runs, their roofline fractions, the FP32/FP16 error against the FP64 run
+(area-weighted relative L2 of rho - 1, u and vorticity after warmup + steps)
+and the CPU oracle's throughput on the same grid are reported alongside.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+N_THETA, N_PHI, TAU = 2048, 4096, 1e-5
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
+KERNEL_NAME = {"f64": "stage_kernel<StF64>", "f32": "stage_kernel<StF32>", "f16": "stage_kernel<StF16>"}
+# algorithmic population traffic per cell and RK step: stage 1 reads f_n and writes
+# f1 (32 values), stages 2 and 3 read their input and f_n and write (48 each)
+VALUES_PER_CELL_STEP = 128
+
+
+def kernel_source_digest() -> str:
+    with open(os.path.join(ROOT, "paper_2504_15574_amd", "csrc", "vlbm.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_c3_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha256_16") != kernel_source_digest():
+        return None
+    e = d.get("per_storage", {}).get(storage)
+    if not e:
+        return None
+    return (e["fetch_kib_per_dispatch"] + e["write_kib_per_dispatch"]) * 1024.0 * d["copy_scale"]
+
+
+def area_rel_l2(a, b, w):
+    return float(np.sqrt((w * (a - b) ** 2).sum() / max((w * b ** 2).sum(), 1e-300)))
+
+
+def run_gpu(storage, state, steps, warmup):
+    import torch
+    from paper_2504_15574_amd import Solver, vlbm_stage_launches
+
+    sol = Solver(N_THETA, N_PHI, TAU, storage=storage)
+    sol.init_fields(*state)
+    sol.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    l0 = vlbm_stage_launches(sol.ctx)
+    # the stage kernels run on sol.stream, the stream these events are recorded on
+    ev0.record(sol.stream)
+    sol.step(steps)
+    ev1.record(sol.stream)
+    torch.cuda.synchronize()
+    launches = vlbm_stage_launches(sol.ctx) - l0
+    ms = ev0.elapsed_time(ev1)
+    r, ut, up = sol.moments(with_T=False)
+    om = sol.vorticity()
+    diag = sol.diagnostics(raise_unstable=False)
+    dt = sol.dt
+    sol.close()
+    del sol
+    torch.cuda.empty_cache()
+    cells = N_THETA * N_PHI
+    b = STORE_BYTES[storage]
+    bytes_per_launch = VALUES_PER_CELL_STEP * b * cells / 3.0
+    avg_launch_s = ms * 1e-3 / launches
+    return {
+        "ms_per_step": ms / steps,
+        "mlups": cells * steps / (ms * 1e-3) / 1e6,
+        "launches": launches,
+        "avg_launch_us": avg_launch_s * 1e6,
+        "achieved_gbs": bytes_per_launch / avg_launch_s / 1e9,
+        "bytes_per_launch": bytes_per_launch,
+        "dt": dt,
+        "fields": (r, ut, up, om),
+        "finite": bool(diag[4] == 0),
+    }
+
+
+def cpu_baseline(state, threads):
+    import oracle
+
+    f = oracle.init(*state)
+    t0 = time.perf_counter()
+    oracle.step(f, 1, tau=TAU, dt=oracle.suggest_dt(N_THETA, N_PHI, TAU), threads=threads)
+    el = time.perf_counter() - t0
+    return {"value": round(N_THETA * N_PHI / el / 1e6, 4), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one SSP-RK3 step of the full {N_THETA}x{N_PHI} turbulence grid, "
+                      f"FP64 plain-C oracle, OpenMP over theta rows, {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--storages", default="f32,f64,f16",
+                    help="comma list; the first is the headline value")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (5 times); "
+                         "calibrates the HBM byte counters against a known traffic")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one MI355X only: --gpus {args.gpus} (WORLD_SIZE {world}) "
+              "is not supported; the multi-GPU layout (theta bands with halo exchange) is "
+              "described but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "copies": 5}))
+        return
+    storages = args.storages.split(",")
+    t0 = time.time()
+    state = W.turbulence_state(N_THETA, N_PHI, seed=0, lmax=256, urms=0.05)
+    print(f"[bench] initial state built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    res = {}
+    for s in storages:
+        torch.cuda.synchronize()
+        res[s] = run_gpu(s, state, args.steps, args.warmup)
+        print(f"[bench] {s}: {res[s]['mlups']:.0f} MLUPS, {res[s]['ms_per_step']:.3f} ms/step, "
+              f"{res[s]['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+
+    head = storages[0]
+    h = res[head]
+    traffic = measured_traffic(head)
+    out = {
+        "metric": "MLUPS (2048x4096,Q=16) FP32-store vs FP64 at <=1e-4 rel err; % HBM peak",
+        "value": round(h["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": "decaying turbulence on the sphere, 2048x4096 cells, D2Q16, "
+                               f"{head} deviation store",
+                   "n_theta": N_THETA, "n_phi": N_PHI, "q": 16, "tau": TAU,
+                   "dt": h["dt"], "storage": head, "seed": 0},
+        "roofline": {"bound": "hbm", "achieved": round(h["achieved_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(h["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": round(traffic, 1) if traffic else None,
+                     "kernel": KERNEL_NAME[head],
+                     "avg_launch_us": round(h["avg_launch_us"], 2),
+                     "algorithmic_bytes_per_launch": h["bytes_per_launch"]},
+    }
+    per = {}
+    for s in storages:
+        per[s] = {"mlups": round(res[s]["mlups"], 1), "ms_per_step": round(res[s]["ms_per_step"], 4),
+                  "hbm_frac_algorithmic": round(res[s]["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                  "avg_launch_us": round(res[s]["avg_launch_us"], 2), "finite": res[s]["finite"]}
+    out["per_storage"] = per
+    if "f64" in res and "f32" in res:
+        out["f32_over_f64_mlups"] = round(res["f32"]["mlups"] / res["f64"]["mlups"], 3)
+
+    if not args.no_precision and "f64" in res:
+        th = (np.arange(N_THETA) + 0.5) * np.pi / N_THETA
+        w = np.sin(th)[:, None] * np.ones((1, N_PHI))
+        r64, a64, b64, o64 = res["f64"]["fields"]
+        prec = {}
+        for s in storages:
+            if s == "f64":
+                continue
+            r, a, b, o = res[s]["fields"]
+            du = np.sqrt(((w * ((a - a64) ** 2 + (b - b64) ** 2)).sum())
+                         / (w * (a64 ** 2 + b64 ** 2)).sum())
+            prec[f"{s}_vs_f64"] = {"rho": area_rel_l2(r, r64, w),
+                                   "rho_minus_1": area_rel_l2(r - 1.0, r64 - 1.0, w),
+                                   "u": float(du), "vorticity": area_rel_l2(o, o64, w),
+                                   "after_steps": args.warmup + args.steps}
+        out["precision"] = prec
+
+    if not args.no_cpu_baseline:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        print(f"[bench] CPU oracle baseline on {threads} threads ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(state, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

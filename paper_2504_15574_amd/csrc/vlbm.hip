@@ -59,6 +59,10 @@ struct Consts {
     double Kt[NQ * NQ];   // K~^H
     double scale[NK];     // FP16 storage scale 2^e_k (1 for the other formats)
     double iscale[NK];    // 1 / scale
+    // rank-1 form of the inertial force: population (kt, kp) adds
+    //   fa[kp][a][kt] * cot g  to G_(a, kp)   and   fb[kt][b][kp] * cot g  to G_(kt, b)
+    double fa[NQ * NQ * NQ];   // -v_kp^2 K[a][kt]
+    double fb[NQ * NQ * NQ];   //  v_kt Kt[b][kp]
 };
 
 // per-row tables in the workspace (FP64)
@@ -67,8 +71,8 @@ struct Rows {
     const double* inv_sdth;  // [nt]: 1 / (R sin th_s dth)
     const double* inv_sdph;  // [nt]: 1 / (R sin th_s dph)
     const double* cot;       // [nt]: cos th_s / (R sin th_s)
-    const double* rest;      // [16][nt]: L of the rest state w_k rho0
-    const double* dC;        // [2][nt + 1][2]: C1 - C2, C3 - C2 of sin th per interface
+    const double* rest;      // [16][nt]: dt * L of the rest state w_k rho0 at central-candidate weights
+    const double* dC;        // [2][nt + 1][2]: rho0 (C1 - C2), rho0 (C3 - C2) of sin th per interface
 };
 
 struct StageArgs {
@@ -104,34 +108,42 @@ struct StF16 {
 };
 
 // ---------------------------------------------------------------------------
-// WENO-5 interface flux for a positive advection velocity (eqs. (fluxes_W5),
-// (WENO5_delta), (WENO5_sigma)) from the points s-2..s+2.  h: flux function
-// V f at the points, f: the populations of the smoothness indicators (a
-// deviation gives the same indicators).  Returns the flux and the normalised
-// weights omega_1, omega_3 (omega_2 = 1 - omega_1 - omega_3).
+// WENO-5 interface flux for an upwind direction, eqs. (fluxes_W5), (WENO5_delta),
+// (WENO5_sigma), from the five stencil points in upwind order (s-2 .. s+2 for a
+// positive velocity, the mirror s+3 .. s-1 for a negative one).  h: flux
+// function at the points; g: the values of the smoothness indicators (a
+// deviation from a uniform state gives the same indicators).
+//   F = F2 + w1 (F1 - F2) + w3 (F3 - F2),  w_i = (d_i / q_i) / sum_j (d_j / q_j),
+//   q_i = (eps + sigma_i)^2.
+// The indicators are carried scaled by 12 (13 a^2 + 3 b^2 with eps scaled to
+// match), which leaves the normalised weights unchanged, and the weights are
+// normalised with a single reciprocal.  c1, c3 add rest-state candidate
+// differences that share the weights (zero for the phi direction).
+template <class T> __device__ __forceinline__ T rcp_(T x);
+template <> __device__ __forceinline__ float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp_<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);      // one Newton step on the hardware estimate
+    return fma(r, e, r);
+}
+
 template <class T>
-__device__ __forceinline__ T weno5p(T h0, T h1, T h2, T h3, T h4, T f0, T f1, T f2, T f3, T f4,
-                                    T eps, T& o1, T& o3) {
-    const T c13 = T(1.0 / 3.0), c16 = T(1.0 / 6.0), c56 = T(5.0 / 6.0);
-    const T c76 = T(7.0 / 6.0), c116 = T(11.0 / 6.0), c1312 = T(13.0 / 12.0);
-    T F1 = c13 * h0 - c76 * h1 + c116 * h2;
-    T F2 = -c16 * h1 + c56 * h2 + c13 * h3;
-    T F3 = c13 * h2 + c56 * h3 - c16 * h4;
-    T a1 = f0 - T(2) * f1 + f2, b1 = f0 - T(4) * f1 + T(3) * f2;
-    T a2 = f1 - T(2) * f2 + f3, b2 = f1 - f3;
-    T a3 = f2 - T(2) * f3 + f4, b3 = T(3) * f2 - T(4) * f3 + f4;
-    T s1 = c1312 * a1 * a1 + T(0.25) * b1 * b1;
-    T s2 = c1312 * a2 * a2 + T(0.25) * b2 * b2;
-    T s3 = c1312 * a3 * a3 + T(0.25) * b3 * b3;
-    T e1 = eps + s1, e2 = eps + s2, e3 = eps + s3;
-    T q1 = e1 * e1, q2 = e2 * e2, q3 = e3 * e3;
-    // alpha_i = delta_i / q_i normalised with one reciprocal
-    T n1 = T(0.1) * (q2 * q3), n2 = T(0.6) * (q1 * q3), n3 = T(0.3) * (q1 * q2);
-    T r = T(1) / (n1 + n2 + n3);
-    o1 = n1 * r;
-    o3 = n3 * r;
-    T o2 = n2 * r;
-    return o1 * F1 + o2 * F2 + o3 * F3;
+__device__ __forceinline__ T weno5(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g2, T g3, T g4,
+                                   T eps12, T c1, T c3) {
+    const T F2 = (T(5) * h2 + T(2) * h3 - h1) * T(1.0 / 6.0);
+    const T d1 = (h0 - h3 + T(3) * (h2 - h1)) * T(1.0 / 3.0);    // F1 - F2
+    const T d3 = (h1 - h4 + T(3) * (h3 - h2)) * T(1.0 / 6.0);    // F3 - F2
+    const T D0 = g1 - g0, D1 = g2 - g1, D2 = g3 - g2, D3 = g4 - g3;
+    const T a1 = D1 - D0, a2 = D2 - D1, a3 = D3 - D2;
+    const T b1 = a1 + T(2) * D1, b2 = D1 + D2, b3 = a3 - T(2) * D2;
+    const T e1 = eps12 + T(13) * a1 * a1 + T(3) * b1 * b1;
+    const T e2 = eps12 + T(13) * a2 * a2 + T(3) * b2 * b2;
+    const T e3 = eps12 + T(13) * a3 * a3 + T(3) * b3 * b3;
+    const T q1 = e1 * e1, q2 = e2 * e2, q3 = e3 * e3;
+    const T n1 = q2 * q3, n3 = T(3) * (q1 * q2);
+    const T den = n1 + n3 + T(6) * (q1 * q3);
+    const T r = rcp_(den);
+    return F2 + r * (n1 * (d1 + c1) + n3 * (d3 + c3));
 }
 
 __device__ __forceinline__ int wrap(int q, int np) {
@@ -140,149 +152,224 @@ __device__ __forceinline__ int wrap(int q, int np) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused RK stage.  Tile: 4 theta rows x 64 phi columns, one cell per thread
-// (wave w owns row s0 + w, lane l column q0 + l).  Populations are processed
-// one at a time: the population's tile plus a 3-cell halo is staged in LDS
-// (pole rows gathered from column q + np/2 and population 15 - k), both
-// interface fluxes of each direction are formed from LDS, and the centre
-// values are kept in registers for the cell-local terms at the end.
-constexpr int TQ = 64, TS = 4, LR = TS + 2 * NGH, LC = TQ + 2 * NGH, LN = LR * LC;
+// Fused RK stage.
+//
+// Tile: 15 theta rows x 16 phi columns per 256-thread workgroup.  With this
+// shape the 16 x 16 theta interfaces and the 15 x 17 phi interfaces of a tile
+// are one WENO evaluation per thread each, so every interface flux is computed
+// exactly once and exchanged through LDS.  Populations are processed one at a
+// time; each population's tile with its 3-cell cross-shaped halo (pole rows
+// gathered from column q + np/2 and population 15 - k, phi periodic) sits in a
+// triple-buffered LDS slot, so the global loads of population k+2 overlap the
+// fluxes of population k and one barrier per population suffices.  The 240
+// cell threads accumulate dt*L for all 16 populations in registers: advection,
+// the rest-state table, -g/tau and the rank-1 updates of the inertial force;
+// the equilibrium is added at the end from the accumulated moments.
+// Workgroups are numbered so that those sharing an XCD (dispatched round-robin
+// over the 8 XCDs) take a contiguous range of tiles, keeping halo rows and the
+// 64-byte halves of shared cache lines inside one L2.
+constexpr int TS = 15, TQ = 16, NTHR = 256;
+constexpr int LR = TS + 2 * NGH, LC = TQ + 2 * NGH, LT = LR * LC;   // 21 x 22
+constexpr int NLOAD = LR * TQ + TS * 2 * NGH;                       // 426 cross-shaped values
+constexpr int NFT = (TS + 1) * TQ;                                  // 256 theta interfaces
+constexpr int NFP = TS * (TQ + 1);                                  // 255 phi interfaces
+static_assert(NFT == NTHR && NFP <= NTHR && NLOAD <= 2 * NTHR && TS * TQ <= NTHR, "tile shape");
+
+__host__ __device__ inline int n_tiles(int nt, int np) {
+    return ((nt + TS - 1) / TS) * ((np + TQ - 1) / TQ);
+}
 
 template <class St>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     using T = typename St::T;
     using S = typename St::S;
-    __shared__ T tile[2][LR][LC];
+    __shared__ T tile[3][LT];
+    __shared__ T fth[2][NFT];
+    __shared__ T fph[2][NFP + 1];
 
-    const int nt = A.nt, np = A.np;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int q0 = blockIdx.x * TQ, s0 = blockIdx.y * TS;
-    const int s = s0 + wv, q = q0 + lane;
-    const bool valid = (s < nt) && (q < np);
-    const int sc = s < nt ? s : nt - 1;
-    const S* __restrict__ gin = static_cast<const S*>(A.gin);
+    const int nt = A.nt, np = A.np, tid = threadIdx.x;
+    const int tq = (np + TQ - 1) / TQ, nb = n_tiles(nt, np);
+    const int per = (nb + 7) / 8;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= nb) return;                       // whole workgroup leaves before any barrier
+    const int s0 = (t / tq) * TS, q0 = (t % tq) * TQ;
     const size_t plane = (size_t)nt * np;
     const int half = np > 1 ? np / 2 : 0;
+    const S* __restrict__ gin = static_cast<const S*>(A.gin);
 
-    auto load_tile = [&](int k, int buf) {
-        const double isc = A.c.iscale[k];
-        for (int idx = threadIdx.x; idx < LN; idx += 256) {
-            int r = idx / LC, cc = idx - r * LC;
-            int ss = s0 - NGH + r, qq = wrap(q0 - NGH + cc, np);
-            int kk = k;
-            if (ss < 0) {                 // north pole: row -m <- row m-1, phi + pi, v -> -v
-                ss = -1 - ss;
-                kk = NK - 1 - k;
-                qq = wrap(qq + half, np);
-            } else if (ss >= nt) {        // south pole: row nt-1+m <- row nt-m
-                ss = 2 * nt - 1 - ss;
-                kk = NK - 1 - k;
-                qq = wrap(qq + half, np);
-            }
-            ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows never used by a valid cell
-            tile[buf][r][cc] = St::ld(gin, (size_t)kk * plane + (size_t)ss * np + qq, isc);
+    // ---- load descriptors: two cross-shaped tile slots per thread
+    int ldst[2], lsrc[2];
+    bool lmir[2], lhas[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int idx = tid + NTHR * j;
+        int r, c;
+        if (idx < LR * TQ) {
+            r = idx / TQ;
+            c = idx % TQ + NGH;
+        } else {
+            const int e = idx - LR * TQ, e2 = e % (TS * NGH);
+            r = e2 / NGH + NGH;
+            c = (e < TS * NGH) ? e2 % NGH : TQ + NGH + e2 % NGH;
         }
+        lhas[j] = idx < NLOAD;
+        int ss = s0 - NGH + r, qq = wrap(q0 - NGH + c, np);
+        bool mir = false;
+        if (ss < 0) {                   // north pole: row -m <- row m-1 at phi + pi, v -> -v
+            ss = -1 - ss;
+            mir = true;
+            qq = wrap(qq + half, np);
+        } else if (ss >= nt) {          // south pole: row nt-1+m <- row nt-m
+            ss = 2 * nt - 1 - ss;
+            mir = true;
+            qq = wrap(qq + half, np);
+        }
+        ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
+        ldst[j] = r * LC + c;
+        lsrc[j] = ss * np + qq;
+        lmir[j] = mir;
+    }
+    auto gload = [&](int k, int j) -> T {
+        const int kk = lmir[j] ? NK - 1 - k : k;
+        return St::ld(gin, (size_t)kk * plane + lsrc[j], A.c.iscale[k]);
     };
 
-    const T eps = T(A.eps);
-    const T rho0 = T(A.rho0);
-    const T isdth = T(A.rows.inv_sdth[sc]);
-    const T isdph = T(A.rows.inv_sdph[sc]);
-    T sn[7];
+    // ---- theta interface of this thread: between tile rows ti-1 and ti, column tc
+    const int ti = tid / TQ, tc = tid % TQ;
+    const int tbase = ti * LC + tc + NGH;                // LDS rows ti .. ti+5 = cell rows s0+ti-3 ..
+    T sn6[6];
 #pragma unroll
-    for (int m = 0; m < 7; ++m) sn[m] = T(A.rows.sinv[sc + m]);   // rows s-3 .. s+3
+    for (int m = 0; m < 6; ++m) {
+        int j = s0 + ti + m;                             // sin table index of row s0+ti-3+m
+        sn6[m] = T(A.rows.sinv[j < nt + 2 * NGH ? j : nt + 2 * NGH - 1]);
+    }
+    const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
+    const T dCp1 = T(A.rows.dC[2 * ig]), dCp3 = T(A.rows.dC[2 * ig + 1]);
+    const T dCm1 = T(A.rows.dC[2 * (nt + 1) + 2 * ig]), dCm3 = T(A.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
+    // ---- phi interface of this thread: row pr, between columns pj-1 and pj
+    const int pr = tid / (TQ + 1), pj = tid % (TQ + 1);
+    const bool phas = tid < NFP;
+    const int pbase = (pr + NGH) * LC + pj;              // LDS columns pj .. pj+5
+    // ---- cell of this thread
+    const int cr = tid / TQ, cc = tid % TQ;
+    const int cs = s0 + cr, cq = q0 + cc;
+    const bool cell = tid < TS * TQ;
+    const bool valid = cell && cs < nt && cq < np;
+    const int csc = cs < nt ? cs : nt - 1;
+    const T dt = T(A.dt);
+    const T dsth = dt * T(A.rows.inv_sdth[csc]);
+    const T dsph = dt * T(A.rows.inv_sdph[csc]);
+    const T dtcot = dt * T(A.rows.cot[csc]);
+    const T keep = T(1) - dt * T(A.inv_tau);
+    const T eps12 = T(12.0 * A.eps);
 
-    T acc[NK], gc[NK];
+    T acc[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) acc[k] = T(0);
+    T drho = T(0), jt = T(0), jp = T(0);
 
-    load_tile(0, 0);
+    // prologue: populations 0 and 1 into slots 0 and 1
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (lhas[j]) tile[k][ldst[j]] = gload(k, j);
     __syncthreads();
+
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-        if (k + 1 < NK) load_tile(k + 1, (k + 1) & 1);
-        const int buf = k & 1;
         const int kt = k >> 2, kp = k & 3;
-        const T vt = T(A.c.v[kt]), vp = T(A.c.v[kp]);
-        // theta direction: column of 7 values, flux function h = v sin(theta_j) g_j
-        T g7[7], h7[7], p7[7], hp7[7];
-#pragma unroll
-        for (int m = 0; m < 7; ++m) {
-            g7[m] = tile[buf][wv + m][lane + NGH];
-            h7[m] = vt * sn[m] * g7[m];
-            p7[m] = tile[buf][wv + NGH][lane + m];
-            hp7[m] = vp * p7[m];
+        const int tb = k % 3, fb = k & 1;
+        const T* tl = tile[tb];
+        // global loads of population k+2 (stored after the barrier)
+        T nx0 = T(0), nx1 = T(0);
+        if (k + 2 < NK) {
+            if (lhas[0]) nx0 = gload(k + 2, 0);
+            if (lhas[1]) nx1 = gload(k + 2, 1);
         }
-        T o1p, o3p, o1m, o3m, Ftp, Ftm, Fpp, Fpm, d1, d2;
-        const int dir = kt >= 2 ? 0 : 1;   // v_theta > 0 for kt = 2, 3
-        if (dir == 0) {
-            Ftp = weno5p(h7[1], h7[2], h7[3], h7[4], h7[5], g7[1], g7[2], g7[3], g7[4], g7[5], eps, o1p, o3p);
-            Ftm = weno5p(h7[0], h7[1], h7[2], h7[3], h7[4], g7[0], g7[1], g7[2], g7[3], g7[4], eps, o1m, o3m);
-        } else {
-            Ftp = weno5p(h7[6], h7[5], h7[4], h7[3], h7[2], g7[6], g7[5], g7[4], g7[3], g7[2], eps, o1p, o3p);
-            Ftm = weno5p(h7[5], h7[4], h7[3], h7[2], h7[1], g7[5], g7[4], g7[3], g7[2], g7[1], eps, o1m, o3m);
-        }
-        // rest-state part of the theta flux beyond its linear-weight value
+        // theta flux, h_j = v sin(theta_j) g_j
         {
-            const double* dC = A.rows.dC + (size_t)dir * (nt + 1) * 2;
-            const T vw = vt * T(A.c.wk[k]) * rho0;
-            Ftp += vw * ((o1p - T(0.1)) * T(dC[2 * (sc + 1)]) + (o3p - T(0.3)) * T(dC[2 * (sc + 1) + 1]));
-            Ftm += vw * ((o1m - T(0.1)) * T(dC[2 * sc]) + (o3m - T(0.3)) * T(dC[2 * sc + 1]));
+            const T vt = T(A.c.v[kt]);
+            const T vw = vt * T(A.c.wk[k]);
+            T g[6], h[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                g[m] = tl[tbase + m * LC];
+                h[m] = (vt * sn6[m]) * g[m];
+            }
+            T F;
+            if (kt >= 2)
+                F = weno5(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4], eps12,
+                          vw * dCp1, vw * dCp3);
+            else
+                F = weno5(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1], eps12,
+                          vw * dCm1, vw * dCm3);
+            fth[fb][tid] = F;
         }
-        if (kp >= 2) {
-            Fpp = weno5p(hp7[1], hp7[2], hp7[3], hp7[4], hp7[5], p7[1], p7[2], p7[3], p7[4], p7[5], eps, d1, d2);
-            Fpm = weno5p(hp7[0], hp7[1], hp7[2], hp7[3], hp7[4], p7[0], p7[1], p7[2], p7[3], p7[4], eps, d1, d2);
-        } else {
-            Fpp = weno5p(hp7[6], hp7[5], hp7[4], hp7[3], hp7[2], p7[6], p7[5], p7[4], p7[3], p7[2], eps, d1, d2);
-            Fpm = weno5p(hp7[5], hp7[4], hp7[3], hp7[2], hp7[1], p7[5], p7[4], p7[3], p7[2], p7[1], eps, d1, d2);
+        // phi flux, h = v g (linear part scaled by v after the reconstruction)
+        if (phas) {
+            T g[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) g[m] = tl[pbase + m];
+            T F;
+            if (kp >= 2)
+                F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
+            else
+                F = weno5(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1], eps12, T(0), T(0));
+            fph[fb][tid] = T(A.c.v[kp]) * F;
         }
-        acc[k] = T(A.rows.rest[(size_t)k * nt + sc]) - isdth * (Ftp - Ftm) - isdph * (Fpp - Fpm);
-        gc[k] = g7[3];
-        // keep this population's arithmetic ahead of the barrier: sinking it past
-        // the barriers would keep every population's stencil live at once
-        asm volatile("" ::"v"(acc[k]));
         __syncthreads();
+        if (cell) {
+            const T gc = tl[(cr + NGH) * LC + cc + NGH];
+            const T Ft = fth[fb][cr * TQ + cc], Fb = fth[fb][(cr + 1) * TQ + cc];
+            const T Fl = fph[fb][cr * (TQ + 1) + cc], Fr = fph[fb][cr * (TQ + 1) + cc + 1];
+            const T R = T(A.rows.rest[(size_t)k * nt + csc]);
+            acc[k] += keep * gc + R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
+            const T tg = dtcot * gc;
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) {
+                acc[a * NQ + kp] += T(A.c.fa[(kp * NQ + a) * NQ + kt]) * tg;
+                acc[kt * NQ + a] += T(A.c.fb[(kt * NQ + a) * NQ + kp]) * tg;
+            }
+            drho += gc;
+            jt += T(A.c.v[kt]) * gc;
+            jp += T(A.c.v[kp]) * gc;
+        }
+        if (k + 2 < NK) {
+            T* nt_ = tile[(k + 2) % 3];
+            if (lhas[0]) nt_[ldst[0]] = nx0;
+            if (lhas[1]) nt_[ldst[1]] = nx1;
+        }
+        // keep this population's register arithmetic in place: deferring it past
+        // the following barriers would keep every population's inputs live at once
+        asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
+                     "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]), "+v"(acc[9]),
+                     "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]), "+v"(acc[14]),
+                     "+v"(acc[15]), "+v"(drho), "+v"(jt), "+v"(jp));
     }
 
     if (!valid) return;
 
-    // cell-local terms on the deviations: inertial force (eqs. (df), (Lf)) and BGK
-    const T cot = T(A.rows.cot[sc]);
-    T v[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) v[i] = T(A.c.v[i]);
-    T drho = 0, jt = 0, jp = 0;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        drho += gc[k];
-        jt += v[k >> 2] * gc[k];
-        jp += v[k & 3] * gc[k];
-    }
+    // equilibrium part of BGK from the accumulated moments (eq. (feq_Q=4))
+    const T rho0 = T(A.rho0);
     const T rho = rho0 + drho;
     const T irho = T(1) / rho;
     const T ut = jt * irho, up = jp * irho;
     const T u2 = ut * ut + up * up;
-    const T itau = T(A.inv_tau), dt = T(A.dt);
+    const T dti = dt * T(A.inv_tau);
     const T ca = T(A.a), cb = T(A.b);
     const S* __restrict__ gnp = static_cast<const S*>(A.gn);
     S* outp = static_cast<S*>(A.out);
-    const size_t cell = (size_t)s * np + q;
+    const size_t cell_off = (size_t)cs * np + cq;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-        const int kt = k >> 2, kp = k & 3;
-        T dfdvt = 0, dfvdvp = 0;
-#pragma unroll
-        for (int b = 0; b < NQ; ++b) {
-            dfdvt += T(A.c.K[kt * NQ + b]) * gc[b * NQ + kp];
-            dfvdvp += T(A.c.Kt[kp * NQ + b]) * gc[kt * NQ + b];
-        }
-        const T G = -cot * (v[kp] * v[kp] * dfdvt - v[kt] * dfvdvp);
-        const T xi = v[kt] * ut + v[kp] * up;
+        const T vt = T(A.c.v[k >> 2]), vp = T(A.c.v[k & 3]);
+        const T xi = vt * ut + vp * up;
         const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
-        const T C = (T(A.c.wk[k]) * (drho + rho * pm1) - gc[k]) * itau;
-        const T L = acc[k] + G + C;
-        const T y = gc[k] + dt * L;
+        const T y = acc[k] + dti * T(A.c.wk[k]) * (drho + rho * pm1);
         T o = cb * y;
-        if (ca != T(0)) o += ca * St::ld(gnp, (size_t)k * plane + cell, A.c.iscale[k]);
-        St::st(outp, (size_t)k * plane + cell, o, A.c.scale[k]);
+        if (ca != T(0)) o += ca * St::ld(gnp, (size_t)k * plane + cell_off, A.c.iscale[k]);
+        St::st(outp, (size_t)k * plane + cell_off, o, A.c.scale[k]);
     }
 }
 
@@ -503,6 +590,12 @@ void build_consts(Consts& c, int storage) {
             c.K[i * NQ + j] = -w1[i] * a;
             c.Kt[i * NQ + j] = -w1[i] * b;
         }
+    for (int kt = 0; kt < NQ; ++kt)
+        for (int kp = 0; kp < NQ; ++kp)
+            for (int a = 0; a < NQ; ++a) {
+                c.fa[(kp * NQ + a) * NQ + kt] = -c.v[kp] * c.v[kp] * c.K[a * NQ + kt];
+                c.fb[(kt * NQ + a) * NQ + kp] = c.v[kt] * c.Kt[a * NQ + kp];
+            }
     for (int k = 0; k < NK; ++k) {
         double sc = 1.0;
         if (storage == VLBM_STORE_F16_DEV) sc = std::ldexp(1.0, 10 - (int)std::lround(std::log2(c.wk[k])));
@@ -511,10 +604,13 @@ void build_consts(Consts& c, int storage) {
     }
 }
 
-// Rest-state tables for a grid.  With g = 0 the populations are w_k rho0; the
-// theta flux then has smoothness indicators sigma = 0 only where the data are
-// uniform, so the kernel adds the nonlinear-weight part from dC at run time and
-// the linear-weight part is folded into rest[] together with the force on w rho0.
+// Rest-state tables for a grid.  With g = 0 the populations are w_k rho0.  The
+// theta flux of the rest state at an interface is v_k w_k rho0 times the WENO
+// combination of the candidates C1, C2, C3 of S_j = sin(theta_j):
+//   C2 + w1 (C1 - C2) + w3 (C3 - C2),
+// where the weights are those of the actual data (the indicators of g).  The
+// C2 part and the inertial force on w_k rho0 are exact per row and go into
+// rest[] (times dt); the kernel adds w1 (C1 - C2) + w3 (C3 - C2) from dC.
 struct HostRows {
     std::vector<double> sinv, inv_sdth, inv_sdph, cot, rest, dC;
 };
@@ -535,7 +631,7 @@ void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
     }
     // candidate reconstructions of S_j = sin th_j at interface i (= s + 1/2, s = i - 1)
     h.dC.assign(2 * (nt + 1) * 2, 0.0);
-    std::vector<double> clin(2 * (nt + 1));
+    std::vector<double> c2(2 * (nt + 1));
     for (int dir = 0; dir < 2; ++dir)
         for (int i = 0; i <= nt; ++i) {
             const int s = i - 1;
@@ -547,9 +643,9 @@ void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
             const double C1 = P[0] / 3.0 - 7.0 * P[1] / 6.0 + 11.0 * P[2] / 6.0;
             const double C2 = -P[1] / 6.0 + 5.0 * P[2] / 6.0 + P[3] / 3.0;
             const double C3 = P[2] / 3.0 + 5.0 * P[3] / 6.0 - P[4] / 6.0;
-            h.dC[(dir * (nt + 1) + i) * 2 + 0] = C1 - C2;
-            h.dC[(dir * (nt + 1) + i) * 2 + 1] = C3 - C2;
-            clin[dir * (nt + 1) + i] = 0.1 * C1 + 0.6 * C2 + 0.3 * C3;
+            h.dC[(dir * (nt + 1) + i) * 2 + 0] = p.rho0 * (C1 - C2);
+            h.dC[(dir * (nt + 1) + i) * 2 + 1] = p.rho0 * (C3 - C2);
+            c2[dir * (nt + 1) + i] = C2;
         }
     h.rest.assign((size_t)NK * nt, 0.0);
     const double r0 = p.rho0;
@@ -558,14 +654,14 @@ void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
         const int dir = c.v[kt] > 0 ? 0 : 1;
         for (int s = 0; s < nt; ++s) {
             const double vw = c.v[kt] * c.wk[k] * r0;
-            const double adv = -h.inv_sdth[s] * vw * (clin[dir * (nt + 1) + s + 1] - clin[dir * (nt + 1) + s]);
+            const double adv = -h.inv_sdth[s] * vw * (c2[dir * (nt + 1) + s + 1] - c2[dir * (nt + 1) + s]);
             double dfdvt = 0.0, dfvdvp = 0.0;
             for (int b = 0; b < NQ; ++b) {
                 dfdvt += c.K[kt * NQ + b] * c.wk[b * NQ + kp] * r0;
                 dfvdvp += c.Kt[kp * NQ + b] * c.wk[kt * NQ + b] * r0;
             }
             const double G = -h.cot[s] * (c.v[kp] * c.v[kp] * dfdvt - c.v[kt] * dfvdvp);
-            h.rest[(size_t)k * nt + s] = adv + G;
+            h.rest[(size_t)k * nt + s] = p.dt * (adv + G);
         }
     }
 }
@@ -670,8 +766,9 @@ vlbm_status launch_stage(vlbm_ctx* x, int stage) {
     if (stage == 1) { A.gin = fn; A.out = fa; A.a = 0.0; A.b = 1.0; }
     else if (stage == 2) { A.gin = fa; A.out = fb; A.a = 0.75; A.b = 0.25; }
     else { A.gin = fb; A.out = fn; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0; }
-    dim3 grid((np + TQ - 1) / TQ, (nt + TS - 1) / TS);
-    hipLaunchKernelGGL(stage_kernel<St>, grid, dim3(256), 0, x->stream, A);
+    const int nb = n_tiles(nt, np);
+    dim3 grid(8 * ((nb + 7) / 8));
+    hipLaunchKernelGGL(stage_kernel<St>, grid, dim3(NTHR), 0, x->stream, A);
     x->launches++;
     return launch_check();
 }

@@ -89,28 +89,38 @@ def sh_synthesis(coef: dict, n_theta: int, n_phi: int, lmax: int):
     """Evaluate psi = sum a_lm Y_lm (real orthonormal harmonics) and its derivatives.
 
     ``coef[(l, m)]`` for m in -l..l (m < 0: sin(|m| phi), m > 0: cos(m phi)).
-    Returns psi, d psi/d theta, d psi/d phi on the grid."""
+    Returns psi, d psi/d theta, d psi/d phi on the grid.  Each order m is
+    summed over l in theta first; the phi dependence is then synthesised with
+    one inverse real FFT per field (direct sums when n_phi <= 2 lmax)."""
     th, ph = grid(n_theta, n_phi)
-    psi = np.zeros((n_theta, n_phi))
-    dth = np.zeros_like(psi)
-    dph = np.zeros_like(psi)
+    use_fft = n_phi > 2 * lmax
+    nf = n_phi // 2 + 1
+    spec = [np.zeros((n_theta, nf), complex) for _ in range(3)] if use_fft else None
+    out = [np.zeros((n_theta, n_phi)) for _ in range(3)]
+    dph = 2.0 * np.pi / n_phi
     for m in range(0, lmax + 1):
         P, dP = _legendre_columns(lmax, m, th)
         lc = np.arange(m, lmax + 1)
-        if m == 0:
-            a = np.array([coef.get((l, 0), 0.0) for l in lc])
-            psi += (a @ P)[:, None]
-            dth += (a @ dP)[:, None]
-            continue
-        ac = np.sqrt(2.0) * np.array([coef.get((l, m), 0.0) for l in lc])
-        as_ = np.sqrt(2.0) * np.array([coef.get((l, -m), 0.0) for l in lc])
-        cm, sm = np.cos(m * ph), np.sin(m * ph)
-        c_th, s_th = ac @ P, as_ @ P
-        dc_th, ds_th = ac @ dP, as_ @ dP
-        psi += np.outer(c_th, cm) + np.outer(s_th, sm)
-        dth += np.outer(dc_th, cm) + np.outer(ds_th, sm)
-        dph += m * (np.outer(-c_th, sm) + np.outer(s_th, cm))
-    return psi, dth, dph
+        r2 = 1.0 if m == 0 else np.sqrt(2.0)
+        ac = r2 * np.array([coef.get((l, m), 0.0) for l in lc])
+        as_ = r2 * np.array([coef.get((l, -m), 0.0) for l in lc]) if m > 0 else np.zeros(lc.size)
+        A, B = ac @ P, as_ @ P          # psi = sum_m A_m cos(m phi) + B_m sin(m phi)
+        dA, dB = ac @ dP, as_ @ dP
+        if use_fft:
+            # cos/sin(m phi_q) with phi_q = (q + 1/2) dph -> coefficient of e^{i m q dph}
+            sh = np.exp(0.5j * m * dph)
+            w = n_phi if m == 0 else 0.5 * n_phi
+            spec[0][:, m] += w * (A - 1j * B) * sh
+            spec[1][:, m] += w * (dA - 1j * dB) * sh
+            spec[2][:, m] += w * 1j * m * (A - 1j * B) * sh
+        else:
+            cm, sm = np.cos(m * ph), np.sin(m * ph)
+            out[0] += np.outer(A, cm) + np.outer(B, sm)
+            out[1] += np.outer(dA, cm) + np.outer(dB, sm)
+            out[2] += m * (np.outer(-A, sm) + np.outer(B, cm))
+    if use_fft:
+        out = [np.fft.irfft(sp, n=n_phi, axis=1) for sp in spec]
+    return out[0], out[1], out[2]
 
 
 def _velocity_from_streamfunction(dth, dph, th, R=1.0):
