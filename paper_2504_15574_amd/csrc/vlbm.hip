@@ -75,36 +75,82 @@ struct Rows {
     const double* dC;        // [2][nt + 1][2]: rho0 (C1 - C2), rho0 (C3 - C2) of sin th per interface
 };
 
+// the constants the stage kernel uses, in its arithmetic type
+template <class T>
+struct ConstsT {
+    T v[NQ], wk[NK], vw[NK], fa[NQ * NQ * NQ], fb[NQ * NQ * NQ], scale[NK], iscale[NK];
+};
+
 struct StageArgs {
     const void* gin;   // stage input (halo reads)
     const void* gn;    // f_n deviations (point reads), may alias out
     void* out;         // stage output
     Rows rows;
-    Consts c;
+    const void* rest_t;   // rest[] in the arithmetic type of the kernel
+    ConstsT<double> cd;
+    ConstsT<float> cf;
     int nt, np;
     double dt, inv_tau, rho0, eps;
     double a, b;       // out = a g_n + b (g_in + dt L)
 };
 
 // ---------------------------------------------------------------------------
-// storage formats
+// storage formats.  ld/st address flat memory; bld/bst go through a buffer
+// resource (one 32-bit per-lane byte offset plus a wave-uniform scalar byte
+// offset), which keeps 64-bit address arithmetic out of the stage kernel.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    // word 3 = 0x00020000: raw (untyped) 32-bit buffer access on gfx9-family parts
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
 struct StF64 {
     using S = double;
     using T = double;
+    static constexpr int B = 8;
+    __device__ static T rload(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
     __device__ static T ld(const S* p, size_t i, double) { return p[i]; }
     __device__ static void st(S* p, size_t i, T v, double) { p[i] = v; }
+    __device__ static T bld(rsrc_t r, uint32_t vo, uint32_t so, float) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    __device__ static void bst(rsrc_t r, uint32_t vo, uint32_t so, T v, float) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, vo, so, 0);
+    }
 };
 struct StF32 {
     using S = float;
     using T = float;
+    static constexpr int B = 4;
+    __device__ static T rload(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
     __device__ static T ld(const S* p, size_t i, double) { return p[i]; }
     __device__ static void st(S* p, size_t i, T v, double) { p[i] = v; }
+    __device__ static T bld(rsrc_t r, uint32_t vo, uint32_t so, float) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static void bst(rsrc_t r, uint32_t vo, uint32_t so, T v, float) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
 };
 struct StF16 {
     using S = _Float16;
     using T = float;
+    static constexpr int B = 2;
+    __device__ static T rload(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
     __device__ static T ld(const S* p, size_t i, double isc) { return (float)p[i] * (float)isc; }
     __device__ static void st(S* p, size_t i, T v, double sc) { p[i] = (_Float16)(v * (float)sc); }
+    __device__ static T bld(rsrc_t r, uint32_t vo, uint32_t so, float isc) {
+        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)) * isc;
+    }
+    __device__ static void bst(rsrc_t r, uint32_t vo, uint32_t so, T v, float sc) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)(v * sc)), r, vo, so, 0);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -146,6 +192,10 @@ __device__ __forceinline__ T weno5(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g
     return F2 + r * (n1 * (d1 + c1) + n3 * (d3 + c3));
 }
 
+template <class T> __device__ __forceinline__ const ConstsT<T>& consts_of(const StageArgs& A);
+template <> __device__ __forceinline__ const ConstsT<double>& consts_of<double>(const StageArgs& A) { return A.cd; }
+template <> __device__ __forceinline__ const ConstsT<float>& consts_of<float>(const StageArgs& A) { return A.cf; }
+
 __device__ __forceinline__ int wrap(int q, int np) {
     int r = q % np;
     return r < 0 ? r + np : r;
@@ -182,27 +232,36 @@ __host__ __device__ inline int n_tiles(int nt, int np) {
 template <class St>
 __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     using T = typename St::T;
-    using S = typename St::S;
-    __shared__ T tile[3][LT];
+    constexpr int B = St::B;
+    constexpr int PAD = 8;                     // destination of the unused load slots
+    __shared__ T tile[3][LT + PAD];            // g of one population, cross-shaped halo
+    __shared__ T tileh[3][LT + PAD];           // theta flux function v sin(theta_j) g_j
     __shared__ T fth[2][NFT];
     __shared__ T fph[2][NFP + 1];
 
+    const ConstsT<T>& C = consts_of<T>(A);
     const int nt = A.nt, np = A.np, tid = threadIdx.x;
     const int tq = (np + TQ - 1) / TQ, nb = n_tiles(nt, np);
     const int per = (nb + 7) / 8;
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (t >= nb) return;                       // whole workgroup leaves before any barrier
     const int s0 = (t / tq) * TS, q0 = (t % tq) * TQ;
-    const size_t plane = (size_t)nt * np;
+    const uint32_t plane = (uint32_t)nt * (uint32_t)np;
+    const uint32_t planeB = plane * B;
     const int half = np > 1 ? np / 2 : 0;
-    const S* __restrict__ gin = static_cast<const S*>(A.gin);
+    const rsrc_t rin = make_rsrc(A.gin, NK * planeB);
 
-    // ---- load descriptors: two cross-shaped tile slots per thread
-    int ldst[2], lsrc[2];
-    bool lmir[2], lhas[2];
+    // ---- load descriptors: two cross-shaped tile slots per thread.  The byte
+    // offset of population k is (k*planeB ^ m) + a: m = 0 for interior rows,
+    // m = ~0 for pole ghost rows, which then read population 15 - k.
+    uint32_t la[2], lm[2];
+    int ldst[2];
+    T lsin[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const int idx = tid + NTHR * j;
+        int idx = tid + NTHR * j;
+        const bool used = idx < NLOAD;
+        if (!used) idx = 0;
         int r, c;
         if (idx < LR * TQ) {
             r = idx / TQ;
@@ -212,7 +271,6 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             r = e2 / NGH + NGH;
             c = (e < TS * NGH) ? e2 % NGH : TQ + NGH + e2 % NGH;
         }
-        lhas[j] = idx < NLOAD;
         int ss = s0 - NGH + r, qq = wrap(q0 - NGH + c, np);
         bool mir = false;
         if (ss < 0) {                   // north pole: row -m <- row m-1 at phi + pi, v -> -v
@@ -225,24 +283,26 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             qq = wrap(qq + half, np);
         }
         ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
-        ldst[j] = r * LC + c;
-        lsrc[j] = ss * np + qq;
-        lmir[j] = mir;
+        ldst[j] = used ? r * LC + c : LT;
+        la[j] = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
+        lm[j] = mir ? ~0u : 0u;
+        const int js = s0 + r;                        // sin table index of row s0 - 3 + r
+        lsin[j] = T(A.rows.sinv[js < nt + 2 * NGH ? js : nt + 2 * NGH - 1]);
     }
     auto gload = [&](int k, int j) -> T {
-        const int kk = lmir[j] ? NK - 1 - k : k;
-        return St::ld(gin, (size_t)kk * plane + lsrc[j], A.c.iscale[k]);
+        return St::bld(rin, (((uint32_t)k * planeB) ^ lm[j]) + la[j], 0, (float)C.iscale[k]);
+    };
+    auto lstore = [&](int k, int buf, T v0, T v1) {
+        const T vt = C.v[k >> 2];
+        tile[buf][ldst[0]] = v0;
+        tile[buf][ldst[1]] = v1;
+        tileh[buf][ldst[0]] = (vt * lsin[0]) * v0;
+        tileh[buf][ldst[1]] = (vt * lsin[1]) * v1;
     };
 
     // ---- theta interface of this thread: between tile rows ti-1 and ti, column tc
     const int ti = tid / TQ, tc = tid % TQ;
-    const int tbase = ti * LC + tc + NGH;                // LDS rows ti .. ti+5 = cell rows s0+ti-3 ..
-    T sn6[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        int j = s0 + ti + m;                             // sin table index of row s0+ti-3+m
-        sn6[m] = T(A.rows.sinv[j < nt + 2 * NGH ? j : nt + 2 * NGH - 1]);
-    }
+    const int tbase = ti * LC + tc + NGH;                // LDS rows ti .. ti+5
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
     const T dCp1 = T(A.rows.dC[2 * ig]), dCp3 = T(A.rows.dC[2 * ig + 1]);
     const T dCm1 = T(A.rows.dC[2 * (nt + 1) + 2 * ig]), dCm3 = T(A.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
@@ -262,6 +322,8 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const T dtcot = dt * T(A.rows.cot[csc]);
     const T keep = T(1) - dt * T(A.inv_tau);
     const T eps12 = T(12.0 * A.eps);
+    const rsrc_t rrest = make_rsrc(A.rest_t, (uint32_t)(NK * nt * sizeof(T)));
+    const uint32_t rvo = (uint32_t)csc * (uint32_t)sizeof(T);
 
     T acc[NK];
 #pragma unroll
@@ -269,33 +331,31 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     T drho = T(0), jt = T(0), jp = T(0);
 
     // prologue: populations 0 and 1 into slots 0 and 1
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-            if (lhas[j]) tile[k][ldst[j]] = gload(k, j);
+    {
+        const T a0 = gload(0, 0), a1 = gload(0, 1), b0 = gload(1, 0), b1 = gload(1, 1);
+        lstore(0, 0, a0, a1);
+        lstore(1, 1, b0, b1);
+    }
     __syncthreads();
 
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         const int kt = k >> 2, kp = k & 3;
         const int tb = k % 3, fb = k & 1;
-        const T* tl = tile[tb];
         // global loads of population k+2 (stored after the barrier)
         T nx0 = T(0), nx1 = T(0);
         if (k + 2 < NK) {
-            if (lhas[0]) nx0 = gload(k + 2, 0);
-            if (lhas[1]) nx1 = gload(k + 2, 1);
+            nx0 = gload(k + 2, 0);
+            nx1 = gload(k + 2, 1);
         }
-        // theta flux, h_j = v sin(theta_j) g_j
+        // theta flux of h_j = v sin(theta_j) g_j
         {
-            const T vt = T(A.c.v[kt]);
-            const T vw = vt * T(A.c.wk[k]);
+            const T vw = C.vw[k];
             T g[6], h[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
-                g[m] = tl[tbase + m * LC];
-                h[m] = (vt * sn6[m]) * g[m];
+                g[m] = tile[tb][tbase + m * LC];
+                h[m] = tileh[tb][tbase + m * LC];
             }
             T F;
             if (kt >= 2)
@@ -306,40 +366,36 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
                           vw * dCm1, vw * dCm3);
             fth[fb][tid] = F;
         }
-        // phi flux, h = v g (linear part scaled by v after the reconstruction)
+        // phi flux, h = v g (reconstructed on g, scaled by v)
         if (phas) {
             T g[6];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) g[m] = tl[pbase + m];
+            for (int m = 0; m < 6; ++m) g[m] = tile[tb][pbase + m];
             T F;
             if (kp >= 2)
                 F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
             else
                 F = weno5(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1], eps12, T(0), T(0));
-            fph[fb][tid] = T(A.c.v[kp]) * F;
+            fph[fb][tid] = C.v[kp] * F;
         }
         __syncthreads();
         if (cell) {
-            const T gc = tl[(cr + NGH) * LC + cc + NGH];
+            const T gc = tile[tb][(cr + NGH) * LC + cc + NGH];
             const T Ft = fth[fb][cr * TQ + cc], Fb = fth[fb][(cr + 1) * TQ + cc];
             const T Fl = fph[fb][cr * (TQ + 1) + cc], Fr = fph[fb][cr * (TQ + 1) + cc + 1];
-            const T R = T(A.rows.rest[(size_t)k * nt + csc]);
+            const T R = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
             acc[k] += keep * gc + R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
             const T tg = dtcot * gc;
 #pragma unroll
             for (int a = 0; a < NQ; ++a) {
-                acc[a * NQ + kp] += T(A.c.fa[(kp * NQ + a) * NQ + kt]) * tg;
-                acc[kt * NQ + a] += T(A.c.fb[(kt * NQ + a) * NQ + kp]) * tg;
+                acc[a * NQ + kp] += C.fa[(kp * NQ + a) * NQ + kt] * tg;
+                acc[kt * NQ + a] += C.fb[(kt * NQ + a) * NQ + kp] * tg;
             }
             drho += gc;
-            jt += T(A.c.v[kt]) * gc;
-            jp += T(A.c.v[kp]) * gc;
+            jt += C.v[kt] * gc;
+            jp += C.v[kp] * gc;
         }
-        if (k + 2 < NK) {
-            T* nt_ = tile[(k + 2) % 3];
-            if (lhas[0]) nt_[ldst[0]] = nx0;
-            if (lhas[1]) nt_[ldst[1]] = nx1;
-        }
+        if (k + 2 < NK) lstore(k + 2, (k + 2) % 3, nx0, nx1);
         // keep this population's register arithmetic in place: deferring it past
         // the following barriers would keep every population's inputs live at once
         asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
@@ -358,18 +414,18 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const T u2 = ut * ut + up * up;
     const T dti = dt * T(A.inv_tau);
     const T ca = T(A.a), cb = T(A.b);
-    const S* __restrict__ gnp = static_cast<const S*>(A.gn);
-    S* outp = static_cast<S*>(A.out);
-    const size_t cell_off = (size_t)cs * np + cq;
+    const rsrc_t rgn = make_rsrc(A.gn, NK * planeB);
+    const rsrc_t rout = make_rsrc(A.out, NK * planeB);
+    const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-        const T vt = T(A.c.v[k >> 2]), vp = T(A.c.v[k & 3]);
+        const T vt = C.v[k >> 2], vp = C.v[k & 3];
         const T xi = vt * ut + vp * up;
         const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
-        const T y = acc[k] + dti * T(A.c.wk[k]) * (drho + rho * pm1);
+        const T y = acc[k] + dti * C.wk[k] * (drho + rho * pm1);
         T o = cb * y;
-        if (ca != T(0)) o += ca * St::ld(gnp, (size_t)k * plane + cell_off, A.c.iscale[k]);
-        St::st(outp, (size_t)k * plane + cell_off, o, A.c.scale[k]);
+        if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+        St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
     }
 }
 
@@ -675,7 +731,7 @@ size_t store_bytes(int storage) {
 constexpr int RED_BLOCKS = 1024;
 
 struct Layout {
-    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, dC, fields, part, dout, total;
+    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, fields, part, dout, total;
 };
 
 Layout layout_of(const vlbm_params& p) {
@@ -689,6 +745,7 @@ Layout layout_of(const vlbm_params& p) {
     L.inv_sdph = off; off += align_up(sizeof(double) * p.n_theta);
     L.cot = off; off += align_up(sizeof(double) * p.n_theta);
     L.rest = off; off += align_up(sizeof(double) * NK * p.n_theta);
+    L.rest_f = off; off += align_up(sizeof(float) * NK * p.n_theta);
     L.dC = off; off += align_up(sizeof(double) * 4 * (p.n_theta + 1));
     L.fields = off; off += align_up(sizeof(double) * 4 * n);
     L.part = off; off += align_up(sizeof(double) * 8 * RED_BLOCKS);
@@ -706,6 +763,10 @@ vlbm_status check_params(const vlbm_params* p) {
         return fail(VLBM_ERR_ARG, "n_phi must be 1 or even");
     if ((long long)p->n_theta * p->n_phi > (1LL << 31) - 1)
         return fail(VLBM_ERR_ARG, "grid too large");
+    if (p->storage >= 0 && p->storage <= 2 &&
+        (unsigned long long)NK * p->n_theta * p->n_phi * store_bytes(p->storage) > 0xffffffffULL)
+        return fail(VLBM_ERR_UNSUPPORTED,
+                    "one population buffer must stay below 4 GiB (32-bit buffer offsets)");
     if (!(p->radius > 0) || !(p->tau > 0) || !(p->dt > 0) || !(p->rho0 > 0) || !(p->weno_eps > 0))
         return fail(VLBM_ERR_ARG, "radius, tau, dt, rho0 and weno_eps must be > 0");
     if (!std::isfinite(p->radius) || !std::isfinite(p->tau) || !std::isfinite(p->dt) ||
@@ -725,6 +786,8 @@ struct vlbm_ctx {
     char* ws;
     Layout L;
     Consts c;
+    ConstsT<double> cd;
+    ConstsT<float> cf;
     int64_t launches;
     int device;
 };
@@ -745,6 +808,7 @@ vlbm_status launch_check() {
 template <class St>
 vlbm_status launch_stage(vlbm_ctx* x, int stage) {
     StageArgs A;
+    static_assert(sizeof(StageArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
     const int nt = x->p.n_theta, np = x->p.n_phi;
     void* fn = x->ws + x->L.fbuf[0];
     void* fa = x->ws + x->L.fbuf[1];
@@ -755,7 +819,10 @@ vlbm_status launch_stage(vlbm_ctx* x, int stage) {
     A.rows.cot = at<double>(x, x->L.cot);
     A.rows.rest = at<double>(x, x->L.rest);
     A.rows.dC = at<double>(x, x->L.dC);
-    A.c = x->c;
+    A.cd = x->cd;
+    A.cf = x->cf;
+    A.rest_t = (sizeof(typename St::T) == 8) ? static_cast<const void*>(at<double>(x, x->L.rest))
+                                              : static_cast<const void*>(at<float>(x, x->L.rest_f));
     A.nt = nt;
     A.np = np;
     A.dt = x->p.dt;
@@ -827,8 +894,21 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     x->L = L;
     x->launches = 0;
     build_consts(x->c, p->storage);
+    for (int i = 0; i < NQ; ++i) { x->cd.v[i] = x->c.v[i]; x->cf.v[i] = (float)x->c.v[i]; }
+    for (int k = 0; k < NK; ++k) {
+        const double vw = x->c.v[k >> 2] * x->c.wk[k];
+        x->cd.wk[k] = x->c.wk[k]; x->cf.wk[k] = (float)x->c.wk[k];
+        x->cd.vw[k] = vw; x->cf.vw[k] = (float)vw;
+        x->cd.scale[k] = x->c.scale[k]; x->cf.scale[k] = (float)x->c.scale[k];
+        x->cd.iscale[k] = x->c.iscale[k]; x->cf.iscale[k] = (float)x->c.iscale[k];
+    }
+    for (int i = 0; i < NQ * NQ * NQ; ++i) {
+        x->cd.fa[i] = x->c.fa[i]; x->cf.fa[i] = (float)x->c.fa[i];
+        x->cd.fb[i] = x->c.fb[i]; x->cf.fb[i] = (float)x->c.fb[i];
+    }
     HostRows h;
     build_rows(h, *p, x->c);
+    std::vector<float> rest_f(h.rest.begin(), h.rest.end());
     hipError_t e = hipGetDevice(&x->device);
     const struct { size_t off; const std::vector<double>* v; } up[] = {
         {L.sinv, &h.sinv}, {L.inv_sdth, &h.inv_sdth}, {L.inv_sdph, &h.inv_sdph},
@@ -838,6 +918,9 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
         e = hipMemcpyAsync(x->ws + u.off, u.v->data(), u.v->size() * sizeof(double),
                            hipMemcpyHostToDevice, x->stream);
     }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(x->ws + L.rest_f, rest_f.data(), rest_f.size() * sizeof(float),
+                           hipMemcpyHostToDevice, x->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
     if (e != hipSuccess) {
         delete x;
