@@ -306,10 +306,13 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
     const T dCp1 = T(A.rows.dC[2 * ig]), dCp3 = T(A.rows.dC[2 * ig + 1]);
     const T dCm1 = T(A.rows.dC[2 * (nt + 1) + 2 * ig]), dCm3 = T(A.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
-    // ---- phi interface of this thread: row pr, between columns pj-1 and pj
-    const int pr = tid / (TQ + 1), pj = tid % (TQ + 1);
+    // ---- phi interface of this thread: the left face of its cell for the 240
+    // cell threads, the right faces of column 15 for threads 240..254
     const bool phas = tid < NFP;
+    const int pr = tid < TS * TQ ? tid / TQ : tid - TS * TQ;
+    const int pj = tid < TS * TQ ? tid % TQ : TQ;
     const int pbase = (pr + NGH) * LC + pj;              // LDS columns pj .. pj+5
+    const int pslot = pr * (TQ + 1) + pj;
     // ---- cell of this thread
     const int cr = tid / TQ, cc = tid % TQ;
     const int cs = s0 + cr, cq = q0 + cc;
@@ -330,7 +333,10 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     for (int k = 0; k < NK; ++k) acc[k] = T(0);
     T drho = T(0), jt = T(0), jp = T(0);
 
-    // prologue: populations 0 and 1 into slots 0 and 1
+    // Ring of three LDS slots: population p lives in slot p % 3.  Its global
+    // loads are issued at the start of iteration p - 2 and it is written to LDS
+    // after that iteration's barrier, when the slot of population p - 3 has been
+    // read for the last time.
     {
         const T a0 = gload(0, 0), a1 = gload(0, 1), b0 = gload(1, 0), b1 = gload(1, 1);
         lstore(0, 0, a0, a1);
@@ -342,12 +348,15 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     for (int k = 0; k < NK; ++k) {
         const int kt = k >> 2, kp = k & 3;
         const int tb = k % 3, fb = k & 1;
-        // global loads of population k+2 (stored after the barrier)
+        T gself, Ftself, Flself = T(0);
+        // global loads of population k+2 (written to LDS after the barrier)
         T nx0 = T(0), nx1 = T(0);
         if (k + 2 < NK) {
             nx0 = gload(k + 2, 0);
             nx1 = gload(k + 2, 1);
         }
+        // this population's rest-state row value, consumed after the barrier
+        const T R = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
         // theta flux of h_j = v sin(theta_j) g_j
         {
             const T vw = C.vw[k];
@@ -357,6 +366,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
                 g[m] = tile[tb][tbase + m * LC];
                 h[m] = tileh[tb][tbase + m * LC];
             }
+            gself = g[3];                                // this thread's cell (row ti, column tc)
             T F;
             if (kt >= 2)
                 F = weno5(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4], eps12,
@@ -365,6 +375,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
                 F = weno5(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1], eps12,
                           vw * dCm1, vw * dCm3);
             fth[fb][tid] = F;
+            Ftself = F;                                  // top face of this thread's cell
         }
         // phi flux, h = v g (reconstructed on g, scaled by v)
         if (phas) {
@@ -376,14 +387,14 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
                 F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
             else
                 F = weno5(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1], eps12, T(0), T(0));
-            fph[fb][tid] = C.v[kp] * F;
+            Flself = C.v[kp] * F;                        // left face of this thread's cell
+            fph[fb][pslot] = Flself;
         }
         __syncthreads();
         if (cell) {
-            const T gc = tile[tb][(cr + NGH) * LC + cc + NGH];
-            const T Ft = fth[fb][cr * TQ + cc], Fb = fth[fb][(cr + 1) * TQ + cc];
-            const T Fl = fph[fb][cr * (TQ + 1) + cc], Fr = fph[fb][cr * (TQ + 1) + cc + 1];
-            const T R = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
+            const T gc = gself, Ft = Ftself, Fl = Flself;
+            const T Fb = fth[fb][(cr + 1) * TQ + cc];
+            const T Fr = fph[fb][cr * (TQ + 1) + cc + 1];
             acc[k] += keep * gc + R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
             const T tg = dtcot * gc;
 #pragma unroll
