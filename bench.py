@@ -54,7 +54,9 @@ def measured_traffic(storage: str):
     e = d.get("per_storage", {}).get(storage)
     if not e:
         return None
-    return (e["fetch_kib_per_dispatch"] + e["write_kib_per_dispatch"]) * 1024.0 * d["copy_scale"]
+    # each counter scaled by what it reads for a plain copy of known size
+    return 1024.0 * (e["fetch_kib_per_dispatch"] * d["copy_scale_fetch"]
+                     + e["write_kib_per_dispatch"] * d["copy_scale_write"])
 
 
 def area_rel_l2(a, b, w):
