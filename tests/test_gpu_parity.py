@@ -1,8 +1,9 @@
 """GPU (HIP) path vs the CPU FP64 oracle, through the C ABI.
 
 Element-by-element comparisons on seeded inputs at sizes the oracle finishes
-in seconds, spanning several 4 x 64 tiles with ragged tails in theta and phi,
-the axisymmetric (n_phi = 1) case and the pole rows.  FP64 storage must agree
+in seconds, spanning several 15 x 16 tiles with ragged tails in theta and phi,
+the axisymmetric (n_phi = 1) case and the pole rows, and at the full C2 and
+benchmark grids.  FP64 storage must agree
 with the oracle to 1e-12 relative (max-abs over all populations, scaled by
 max |f|); the reduced-precision formats report their error as a number and
 are held to bounds derived from their unit round-off.
@@ -74,10 +75,10 @@ def test_init_matches_oracle_equilibrium():
 
 
 @pytest.mark.parametrize("nt,nph,seed,smooth", [
-    (26, 50, 1, False),      # ragged in theta (26 = 6*4 + 2) and phi (50 < 64)
-    (22, 192, 2, True),      # three phi tiles
+    (26, 50, 1, False),      # ragged in theta (26 = 15 + 11) and phi (50 = 3*16 + 2)
+    (22, 192, 2, True),      # twelve phi tiles
     (37, 1, 3, False),       # axisymmetric, odd n_theta
-    (8, 130, 4, False),      # two full tiles + a 2-column tail; every row is a pole row
+    (8, 130, 4, False),      # one partial tile row; every row is a pole row
 ])
 def test_f64_parity_random_states(nt, nph, seed, smooth):
     st = W.random_state(nt, nph, seed=seed, du=0.05, dT=0.05, smooth=smooth)
@@ -202,3 +203,48 @@ def test_reduced_precision_error_vs_oracle(storage, bound):
     rel, reldev = _errs(fg, fr)
     print(f"  {storage}: max rel {rel:.2e}, deviation-relative {reldev:.2e}")
     assert reldev < bound
+
+
+# ---------------------------------------------------------------- full sizes
+@pytest.mark.parametrize("nt,nph,tau,steps,maker", [
+    (512, 1024, 5e-4, 3, "vorticity"),      # the C2 grid (shear wave + random vorticity)
+    (2048, 4096, 1e-5, 1, "turbulence"),    # the benchmark grid, one full step
+])
+def test_f64_parity_full_size(nt, nph, tau, steps, maker):
+    # Full-size parity in the launch configuration bench.py times: every cell of
+    # every population is compared with the CPU oracle (OpenMP over rows).
+    if maker == "vorticity":
+        st = W.random_vorticity_state(nt, nph, seed=0, lmax=16, amp=1e-4, shear=1e-3)
+    else:
+        st = W.turbulence_state(nt, nph, seed=0, lmax=256, urms=0.05)
+    dt = oracle.suggest_dt(nt, nph, tau)
+    fg, fr = _run_both(st, nt, nph, tau, dt, steps)
+    rel, reldev = _errs(fg, fr)
+    print(f"  {nt}x{nph}: max rel {rel:.2e} (deviation-relative {reldev:.2e})")
+    assert rel <= 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_reduced_precision_full_size_properties(storage):
+    # At the benchmark size the reduced formats stay finite, conserve the
+    # rest-state structure and track the FP64 run: after 20 steps the
+    # area-weighted velocity error is below 1e-5 (f32) / 1e-3 (f16).
+    from paper_2504_15574_amd import Solver
+    nt, nph, tau = 2048, 4096, 1e-5
+    st = W.turbulence_state(nt, nph, seed=0, lmax=256, urms=0.05)
+    res = {}
+    for s in ("f64", storage):
+        sol = Solver(nt, nph, tau, storage=s)
+        sol.init_fields(*st)
+        sol.step(20)
+        d = sol.diagnostics()
+        res[s] = (sol.moments(with_T=False), d)
+        sol.close()
+    (r64, a64, b64), d64 = res["f64"]
+    (r, a, b), d = res[storage]
+    th, _ = W.grid(nt, nph)
+    w = np.sin(th)[:, None]
+    du = np.sqrt((w * ((a - a64) ** 2 + (b - b64) ** 2)).sum() / (w * (a64 ** 2 + b64 ** 2)).sum())
+    print(f"  {storage}: u rel L2 {du:.2e}, mass {d[0]:.15e} vs {d64[0]:.15e}")
+    assert du < (1e-5 if storage == "f32" else 1e-3)
+    assert abs(d[0] - d64[0]) < 1e-6 * d64[0]
