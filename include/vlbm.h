@@ -134,7 +134,34 @@ vlbm_status vlbm_set_populations(vlbm_ctx* ctx, const double* f, int ptr_on_devi
  * n_phi = 1).  Returns 0 for invalid parameters. */
 double vlbm_suggest_dt(const vlbm_params* params);
 
-/* Number of stage-kernel launches issued so far by this context. */
+/* ---- ensembles (many independent runs per launch) ---- */
+
+typedef struct vlbm_graph vlbm_graph;
+
+/* Advance n_ctx independent contexts by n_steps SSP-RK3 steps with one stage
+ * launch per RK stage covering the tiles of all of them (64 contexts per
+ * launch; more are split into several launches).  The contexts may differ in
+ * grid, tau and dt but must share the storage format, the device and the
+ * stream, and appear once each.  Every cell runs the same arithmetic as in
+ * vlbm_step, so the result equals stepping each context alone, bit for bit.
+ * Asynchronous on the shared stream.  Errors: VLBM_ERR_ARG. */
+vlbm_status vlbm_step_batch(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps);
+
+/* Record n_steps >= 1 of vlbm_step_batch(ctxs, n_ctx, .) into a HIP graph
+ * (captured on a private stream; nothing runs now).  The graph refers to the
+ * contexts' workspaces: destroy it before them.  Errors: VLBM_ERR_ARG,
+ * VLBM_ERR_DEVICE (capture or instantiation failed), VLBM_ERR_ALLOC. */
+vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps,
+                              vlbm_graph** out);
+
+/* Replay the recorded steps on the contexts' stream (asynchronous). */
+vlbm_status vlbm_graph_launch(vlbm_graph* graph);
+
+/* Release the graph (not the contexts). */
+vlbm_status vlbm_graph_destroy(vlbm_graph* graph);
+
+/* Number of stage-kernel launches issued so far by this context (a batched
+ * launch counts once for every context it covers). */
 int64_t vlbm_stage_launches(const vlbm_ctx* ctx);
 
 /* Text of the last error on this thread ("" if none). */

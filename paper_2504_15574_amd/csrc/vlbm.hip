@@ -81,17 +81,29 @@ struct ConstsT {
     T v[NQ], wk[NK], vw[NK], fa[NQ * NQ * NQ], fb[NQ * NQ * NQ], scale[NK], iscale[NK];
 };
 
-struct StageArgs {
-    const void* gin;   // stage input (halo reads)
-    const void* gn;    // f_n deviations (point reads), may alias out
-    void* out;         // stage output
+// One run (context) at one RK stage, in device memory inside the context's
+// workspace; written once at creation.
+struct RunDesc {
+    const void* gin;      // stage input (halo reads)
+    const void* gn;       // f_n deviations (point reads), may alias out
+    void* out;            // stage output
     Rows rows;
-    const void* rest_t;   // rest[] in the arithmetic type of the kernel
-    ConstsT<double> cd;
-    ConstsT<float> cf;
+    const float* rest_f;  // rest[] in FP32 for the float kernels
     int nt, np;
     double dt, inv_tau, rho0, eps;
-    double a, b;       // out = a g_n + b (g_in + dt L)
+    double a, b;          // out = a g_n + b (g_in + dt L)
+};
+
+// Kernel arguments of a stage launch over the tiles of up to MAXRUNS runs
+// sharing one storage format (one run for vlbm_step).
+constexpr int MAXRUNS = 64;
+struct StageArgs {
+    ConstsT<double> cd;
+    ConstsT<float> cf;
+    RunDesc run0;                  // the run of a single-run launch, by value
+    int nruns;
+    int tile_start[MAXRUNS + 1];   // prefix sums of the runs' tile counts
+    const RunDesc* desc[MAXRUNS];
 };
 
 // ---------------------------------------------------------------------------
@@ -229,7 +241,7 @@ __host__ __device__ inline int n_tiles(int nt, int np) {
     return ((nt + TS - 1) / TS) * ((np + TQ - 1) / TQ);
 }
 
-template <class St>
+template <class St, bool BATCH>
 __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     using T = typename St::T;
     constexpr int B = St::B;
@@ -240,16 +252,25 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     __shared__ T fph[2][NFP + 1];
 
     const ConstsT<T>& C = consts_of<T>(A);
-    const int nt = A.nt, np = A.np, tid = threadIdx.x;
-    const int tq = (np + TQ - 1) / TQ, nb = n_tiles(nt, np);
-    const int per = (nb + 7) / 8;
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (t >= nb) return;                       // whole workgroup leaves before any barrier
+    const int tid = threadIdx.x;
+    const int nall = A.tile_start[A.nruns];
+    const int per = (nall + 7) / 8;
+    const int tg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tg >= nall) return;                    // whole workgroup leaves before any barrier
+    // a single-run launch reads its run from the kernel arguments; a batched one
+    // looks up the run this tile belongs to (uniform per workgroup)
+    int run = 0;
+    if (BATCH)
+        while (A.tile_start[run + 1] <= tg) ++run;
+    const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
+    const int t = tg - A.tile_start[run];
+    const int nt = D.nt, np = D.np;
+    const int tq = (np + TQ - 1) / TQ;
     const int s0 = (t / tq) * TS, q0 = (t % tq) * TQ;
     const uint32_t plane = (uint32_t)nt * (uint32_t)np;
     const uint32_t planeB = plane * B;
     const int half = np > 1 ? np / 2 : 0;
-    const rsrc_t rin = make_rsrc(A.gin, NK * planeB);
+    const rsrc_t rin = make_rsrc(D.gin, NK * planeB);
 
     // ---- load descriptors: two cross-shaped tile slots per thread.  The byte
     // offset of population k is (k*planeB ^ m) + a: m = 0 for interior rows,
@@ -287,7 +308,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         la[j] = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
         lm[j] = mir ? ~0u : 0u;
         const int js = s0 + r;                        // sin table index of row s0 - 3 + r
-        lsin[j] = T(A.rows.sinv[js < nt + 2 * NGH ? js : nt + 2 * NGH - 1]);
+        lsin[j] = T(D.rows.sinv[js < nt + 2 * NGH ? js : nt + 2 * NGH - 1]);
     }
     auto gload = [&](int k, int j) -> T {
         return St::bld(rin, (((uint32_t)k * planeB) ^ lm[j]) + la[j], 0, (float)C.iscale[k]);
@@ -304,8 +325,8 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const int ti = tid / TQ, tc = tid % TQ;
     const int tbase = ti * LC + tc + NGH;                // LDS rows ti .. ti+5
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
-    const T dCp1 = T(A.rows.dC[2 * ig]), dCp3 = T(A.rows.dC[2 * ig + 1]);
-    const T dCm1 = T(A.rows.dC[2 * (nt + 1) + 2 * ig]), dCm3 = T(A.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
+    const T dCp1 = T(D.rows.dC[2 * ig]), dCp3 = T(D.rows.dC[2 * ig + 1]);
+    const T dCm1 = T(D.rows.dC[2 * (nt + 1) + 2 * ig]), dCm3 = T(D.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
     // ---- phi interface of this thread: the left face of its cell for the 240
     // cell threads, the right faces of column 15 for threads 240..254
     const bool phas = tid < NFP;
@@ -319,13 +340,15 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const bool cell = tid < TS * TQ;
     const bool valid = cell && cs < nt && cq < np;
     const int csc = cs < nt ? cs : nt - 1;
-    const T dt = T(A.dt);
-    const T dsth = dt * T(A.rows.inv_sdth[csc]);
-    const T dsph = dt * T(A.rows.inv_sdph[csc]);
-    const T dtcot = dt * T(A.rows.cot[csc]);
-    const T keep = T(1) - dt * T(A.inv_tau);
-    const T eps12 = T(12.0 * A.eps);
-    const rsrc_t rrest = make_rsrc(A.rest_t, (uint32_t)(NK * nt * sizeof(T)));
+    const T dt = T(D.dt);
+    const T dsth = dt * T(D.rows.inv_sdth[csc]);
+    const T dsph = dt * T(D.rows.inv_sdph[csc]);
+    const T dtcot = dt * T(D.rows.cot[csc]);
+    const T keep = T(1) - dt * T(D.inv_tau);
+    const T eps12 = T(12.0 * D.eps);
+    const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
+                                        : static_cast<const void*>(D.rest_f);
+    const rsrc_t rrest = make_rsrc(rest_t, (uint32_t)(NK * nt * sizeof(T)));
     const uint32_t rvo = (uint32_t)csc * (uint32_t)sizeof(T);
 
     T acc[NK];
@@ -418,15 +441,15 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     if (!valid) return;
 
     // equilibrium part of BGK from the accumulated moments (eq. (feq_Q=4))
-    const T rho0 = T(A.rho0);
+    const T rho0 = T(D.rho0);
     const T rho = rho0 + drho;
     const T irho = T(1) / rho;
     const T ut = jt * irho, up = jp * irho;
     const T u2 = ut * ut + up * up;
-    const T dti = dt * T(A.inv_tau);
-    const T ca = T(A.a), cb = T(A.b);
-    const rsrc_t rgn = make_rsrc(A.gn, NK * planeB);
-    const rsrc_t rout = make_rsrc(A.out, NK * planeB);
+    const T dti = dt * T(D.inv_tau);
+    const T ca = T(D.a), cb = T(D.b);
+    const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
+    const rsrc_t rout = make_rsrc(D.out, NK * planeB);
     const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
@@ -742,7 +765,7 @@ size_t store_bytes(int storage) {
 constexpr int RED_BLOCKS = 1024;
 
 struct Layout {
-    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, fields, part, dout, total;
+    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, fields, part, dout, desc, total;
 };
 
 Layout layout_of(const vlbm_params& p) {
@@ -761,6 +784,7 @@ Layout layout_of(const vlbm_params& p) {
     L.fields = off; off += align_up(sizeof(double) * 4 * n);
     L.part = off; off += align_up(sizeof(double) * 8 * RED_BLOCKS);
     L.dout = off; off += align_up(sizeof(double) * 8);
+    L.desc = off; off += align_up(sizeof(RunDesc) * 3);
     L.total = off;
     return L;
 }
@@ -803,6 +827,17 @@ struct vlbm_ctx {
     int device;
 };
 
+struct vlbm_graph {
+    std::vector<vlbm_ctx*> ctxs;
+    int64_t steps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~vlbm_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 namespace {
 
 template <class T>
@@ -816,41 +851,6 @@ vlbm_status launch_check() {
     return VLBM_OK;
 }
 
-template <class St>
-vlbm_status launch_stage(vlbm_ctx* x, int stage) {
-    StageArgs A;
-    static_assert(sizeof(StageArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
-    const int nt = x->p.n_theta, np = x->p.n_phi;
-    void* fn = x->ws + x->L.fbuf[0];
-    void* fa = x->ws + x->L.fbuf[1];
-    void* fb = x->ws + x->L.fbuf[2];
-    A.rows.sinv = at<double>(x, x->L.sinv);
-    A.rows.inv_sdth = at<double>(x, x->L.inv_sdth);
-    A.rows.inv_sdph = at<double>(x, x->L.inv_sdph);
-    A.rows.cot = at<double>(x, x->L.cot);
-    A.rows.rest = at<double>(x, x->L.rest);
-    A.rows.dC = at<double>(x, x->L.dC);
-    A.cd = x->cd;
-    A.cf = x->cf;
-    A.rest_t = (sizeof(typename St::T) == 8) ? static_cast<const void*>(at<double>(x, x->L.rest))
-                                              : static_cast<const void*>(at<float>(x, x->L.rest_f));
-    A.nt = nt;
-    A.np = np;
-    A.dt = x->p.dt;
-    A.inv_tau = 1.0 / x->p.tau;
-    A.rho0 = x->p.rho0;
-    A.eps = x->p.weno_eps;
-    A.gn = fn;
-    if (stage == 1) { A.gin = fn; A.out = fa; A.a = 0.0; A.b = 1.0; }
-    else if (stage == 2) { A.gin = fa; A.out = fb; A.a = 0.75; A.b = 0.25; }
-    else { A.gin = fb; A.out = fn; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0; }
-    const int nb = n_tiles(nt, np);
-    dim3 grid(8 * ((nb + 7) / 8));
-    hipLaunchKernelGGL(stage_kernel<St>, grid, dim3(NTHR), 0, x->stream, A);
-    x->launches++;
-    return launch_check();
-}
-
 template <class F>
 vlbm_status dispatch(int storage, F&& f) {
     switch (storage) {
@@ -858,6 +858,98 @@ vlbm_status dispatch(int storage, F&& f) {
         case VLBM_STORE_F32_DEV: return f(StF32{});
         default: return f(StF16{});
     }
+}
+
+const RunDesc* desc_of(vlbm_ctx* x, int stage) {
+    return reinterpret_cast<const RunDesc*>(x->ws + x->L.desc) + (stage - 1);
+}
+
+// The three per-stage descriptors of a context (stage 3 writes over f_n).
+void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
+    void* fn = x->ws + x->L.fbuf[0];
+    void* fa = x->ws + x->L.fbuf[1];
+    void* fb = x->ws + x->L.fbuf[2];
+    for (int i = 0; i < 3; ++i) {
+        RunDesc& D = d[i];
+        D.rows.sinv = at<double>(x, x->L.sinv);
+        D.rows.inv_sdth = at<double>(x, x->L.inv_sdth);
+        D.rows.inv_sdph = at<double>(x, x->L.inv_sdph);
+        D.rows.cot = at<double>(x, x->L.cot);
+        D.rows.rest = at<double>(x, x->L.rest);
+        D.rows.dC = at<double>(x, x->L.dC);
+        D.rest_f = at<float>(x, x->L.rest_f);
+        D.nt = x->p.n_theta;
+        D.np = x->p.n_phi;
+        D.dt = x->p.dt;
+        D.inv_tau = 1.0 / x->p.tau;
+        D.rho0 = x->p.rho0;
+        D.eps = x->p.weno_eps;
+        D.gn = fn;
+    }
+    d[0].gin = fn; d[0].out = fa; d[0].a = 0.0;       d[0].b = 1.0;
+    d[1].gin = fa; d[1].out = fb; d[1].a = 0.75;      d[1].b = 0.25;
+    d[2].gin = fb; d[2].out = fn; d[2].a = 1.0 / 3.0; d[2].b = 2.0 / 3.0;
+}
+
+// One RK stage for n contexts of the same storage format, MAXRUNS per launch.
+template <class St>
+vlbm_status launch_stage(vlbm_ctx* const* xs, int n, int stage, hipStream_t stream) {
+    static_assert(sizeof(StageArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
+    for (int c0 = 0; c0 < n; c0 += MAXRUNS) {
+        const int m = n - c0 < MAXRUNS ? n - c0 : MAXRUNS;
+        StageArgs A;
+        A.cd = xs[c0]->cd;
+        A.cf = xs[c0]->cf;
+        A.nruns = m;
+        A.tile_start[0] = 0;
+        for (int i = 0; i < m; ++i) {
+            vlbm_ctx* x = xs[c0 + i];
+            A.desc[i] = desc_of(x, stage);
+            A.tile_start[i + 1] = A.tile_start[i] + n_tiles(x->p.n_theta, x->p.n_phi);
+            x->launches++;
+        }
+        const int nb = A.tile_start[m];
+        if (m == 1) {
+            RunDesc d[3];
+            fill_descs(xs[c0], d);
+            A.run0 = d[stage - 1];
+            hipLaunchKernelGGL((stage_kernel<St, false>), dim3(8 * ((nb + 7) / 8)), dim3(NTHR), 0,
+                               stream, A);
+        } else {
+            hipLaunchKernelGGL((stage_kernel<St, true>), dim3(8 * ((nb + 7) / 8)), dim3(NTHR), 0,
+                               stream, A);
+        }
+        vlbm_status st = launch_check();
+        if (st) return st;
+    }
+    return VLBM_OK;
+}
+
+vlbm_status check_batch(vlbm_ctx* const* xs, int n) {
+    if (!xs || n < 1) return fail(VLBM_ERR_ARG, "empty context list");
+    for (int i = 0; i < n; ++i) {
+        if (!xs[i]) return fail(VLBM_ERR_ARG, "NULL context %d", i);
+        if (xs[i]->p.storage != xs[0]->p.storage)
+            return fail(VLBM_ERR_ARG, "contexts of a batch must share the storage format");
+        if (xs[i]->stream != xs[0]->stream)
+            return fail(VLBM_ERR_ARG, "contexts of a batch must share the stream");
+        if (xs[i]->device != xs[0]->device)
+            return fail(VLBM_ERR_ARG, "contexts of a batch must share the device");
+        for (int j = 0; j < i; ++j)
+            if (xs[j] == xs[i]) return fail(VLBM_ERR_ARG, "context %d appears twice", i);
+    }
+    return VLBM_OK;
+}
+
+vlbm_status step_batch(vlbm_ctx* const* xs, int n, int64_t n_steps, hipStream_t stream) {
+    for (int64_t i = 0; i < n_steps; ++i)
+        for (int stage = 1; stage <= 3; ++stage) {
+            vlbm_status st = dispatch(xs[0]->p.storage, [&](auto tag) {
+                return launch_stage<decltype(tag)>(xs, n, stage, stream);
+            });
+            if (st) return st;
+        }
+    return VLBM_OK;
 }
 
 vlbm_status copy_in(vlbm_ctx* x, double* dst, const double* src, size_t n, int on_dev) {
@@ -932,6 +1024,10 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     if (e == hipSuccess)
         e = hipMemcpyAsync(x->ws + L.rest_f, rest_f.data(), rest_f.size() * sizeof(float),
                            hipMemcpyHostToDevice, x->stream);
+    RunDesc descs[3];
+    fill_descs(x, descs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(x->ws + L.desc, descs, sizeof(descs), hipMemcpyHostToDevice, x->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
     if (e != hipSuccess) {
         delete x;
@@ -974,13 +1070,64 @@ vlbm_status vlbm_init_fields(vlbm_ctx* x, const double* rho, const double* ut, c
 
 vlbm_status vlbm_step(vlbm_ctx* x, int64_t n_steps) {
     if (!x || n_steps < 0) return fail(VLBM_ERR_ARG, "bad context or n_steps < 0");
-    for (int64_t i = 0; i < n_steps; ++i)
-        for (int stage = 1; stage <= 3; ++stage) {
-            vlbm_status st = dispatch(x->p.storage, [&](auto tag) {
-                return launch_stage<decltype(tag)>(x, stage);
-            });
-            if (st) return st;
+    return step_batch(&x, 1, n_steps, x->stream);
+}
+
+vlbm_status vlbm_step_batch(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps) {
+    vlbm_status st = check_batch(ctxs, n_ctx);
+    if (st) return st;
+    if (n_steps < 0) return fail(VLBM_ERR_ARG, "n_steps < 0");
+    return step_batch(ctxs, n_ctx, n_steps, ctxs[0]->stream);
+}
+
+vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps, vlbm_graph** out) {
+    vlbm_status st = check_batch(ctxs, n_ctx);
+    if (st) return st;
+    if (!out || n_steps < 1) return fail(VLBM_ERR_ARG, "bad output pointer or n_steps < 1");
+    vlbm_graph* g = new (std::nothrow) vlbm_graph();
+    if (!g) return fail(VLBM_ERR_ALLOC, "host allocation failed");
+    g->ctxs.assign(ctxs, ctxs + n_ctx);
+    g->steps = n_steps;
+    std::vector<int64_t> before(n_ctx);
+    for (int i = 0; i < n_ctx; ++i) before[i] = ctxs[i]->launches;
+    // capture on a private stream (the null stream cannot be captured); the
+    // graph is launched later on the contexts' stream
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = step_batch(ctxs, n_ctx, n_steps, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (!st && e2 == hipSuccess) {
+            e2 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            if (e2 == hipSuccess) g->graph = graph;
+            else (void)hipGraphDestroy(graph);
+        } else if (graph) {
+            (void)hipGraphDestroy(graph);
         }
+        e = e2;
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    for (int i = 0; i < n_ctx; ++i) ctxs[i]->launches = before[i];
+    if (st || e != hipSuccess) {
+        delete g;
+        return st ? st : fail(VLBM_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_graph_launch(vlbm_graph* g) {
+    if (!g || !g->exec) return fail(VLBM_ERR_ARG, "bad graph");
+    HIP_OK(hipGraphLaunch(g->exec, g->ctxs[0]->stream));
+    for (vlbm_ctx* x : g->ctxs) x->launches += 3 * g->steps;
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_graph_destroy(vlbm_graph* g) {
+    if (!g) return VLBM_OK;
+    delete g;
     return VLBM_OK;
 }
 

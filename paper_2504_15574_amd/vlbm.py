@@ -57,6 +57,11 @@ SIGNATURES = [
     ("vlbm_set_populations", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     ("vlbm_suggest_dt", ctypes.c_double, [_P]),
     ("vlbm_stage_launches", ctypes.c_int64, [_vp]),
+    ("vlbm_step_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64]),
+    ("vlbm_graph_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
+                                         ctypes.POINTER(_vp)]),
+    ("vlbm_graph_launch", ctypes.c_int, [_vp]),
+    ("vlbm_graph_destroy", ctypes.c_int, [_vp]),
     ("vlbm_last_error", ctypes.c_char_p, []),
 ]
 
@@ -153,6 +158,29 @@ def vlbm_stage_launches(ctx) -> int:
     return int(load().vlbm_stage_launches(_vp(ctx)))
 
 
+def _ctx_array(ctxs):
+    return (_vp * len(ctxs))(*[_vp(c) for c in ctxs])
+
+
+def vlbm_step_batch(ctxs, n: int):
+    _check(load().vlbm_step_batch(_ctx_array(ctxs), len(ctxs), int(n)), "vlbm_step_batch")
+
+
+def vlbm_graph_create(ctxs, n: int) -> int:
+    out = _vp()
+    _check(load().vlbm_graph_create(_ctx_array(ctxs), len(ctxs), int(n), ctypes.byref(out)),
+           "vlbm_graph_create")
+    return out.value
+
+
+def vlbm_graph_launch(graph):
+    _check(load().vlbm_graph_launch(_vp(graph)), "vlbm_graph_launch")
+
+
+def vlbm_graph_destroy(graph):
+    _check(load().vlbm_graph_destroy(_vp(graph)), "vlbm_graph_destroy")
+
+
 # ---- convenience object ---------------------------------------------------------
 def _host(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
@@ -231,5 +259,44 @@ class Solver:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Independent runs advanced together: one stage launch per RK stage covers
+    every run (``vlbm_step_batch``), optionally replayed from a HIP graph of
+    ``graph_steps`` steps.  Runs may differ in grid, tau and dt; they share the
+    storage format and torch's current stream."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        self.ctxs = [s.ctx for s in self.solvers]
+        self.graph = None
+        self.graph_steps = 0
+
+    def step(self, n=1):
+        vlbm_step_batch(self.ctxs, n)
+        for s in self.solvers:
+            s.t += n * s.dt
+
+    def capture(self, steps):
+        self.release()
+        self.graph = vlbm_graph_create(self.ctxs, steps)
+        self.graph_steps = steps
+
+    def replay(self):
+        vlbm_graph_launch(self.graph)
+        for s in self.solvers:
+            s.t += self.graph_steps * s.dt
+
+    def release(self):
+        if self.graph:
+            vlbm_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.release()
         except Exception:
             pass

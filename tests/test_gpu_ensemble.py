@@ -1,0 +1,123 @@
+"""Ensembles: many independent runs advanced by shared stage launches.
+
+A batched launch covers the tiles of several contexts; every cell runs the same
+arithmetic as in a single-context launch, so batched and one-by-one stepping
+must agree bit for bit.  HIP-graph replays of recorded steps must equal eager
+stepping, also with other work queued between replays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    from paper_2504_15574_amd import load
+    load()
+
+
+def _runs(storage, specs, seed=0):
+    from paper_2504_15574_amd import Solver
+    rng = np.random.default_rng(seed)
+    out = []
+    for nt, nph in specs:
+        tau = float(rng.uniform(1e-3, 5e-3))
+        s = Solver(nt, nph, tau, storage=storage)
+        s.init_fields(*W.random_state(nt, nph, seed=int(rng.integers(1 << 30)), du=0.05,
+                                      dT=0.05, smooth=False))
+        out.append(s)
+    return out
+
+
+SPECS = [(32, 64), (32, 64), (48, 96), (20, 1), (16, 130), (64, 128)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_batched_equals_one_by_one_bitwise(storage):
+    from paper_2504_15574_amd import Ensemble, vlbm_stage_launches
+    a = _runs(storage, SPECS, seed=1)
+    b = _runs(storage, SPECS, seed=1)
+    ens = Ensemble(a)
+    ens.step(7)
+    for s in b:
+        s.step(7)
+    for x, y in zip(a, b):
+        assert vlbm_stage_launches(x.ctx) == 21
+        assert np.array_equal(x.populations(), y.populations())
+    for s in a + b:
+        s.close()
+
+
+def test_more_than_64_runs_split_into_launches():
+    from paper_2504_15574_amd import Ensemble
+    specs = [(8, 16)] * 40 + [(12, 32)] * 30
+    a = _runs("f32", specs, seed=2)
+    b = _runs("f32", specs, seed=2)
+    Ensemble(a).step(3)
+    for s in b:
+        s.step(3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.populations(), y.populations())
+    for s in a + b:
+        s.close()
+
+
+def test_graph_replays_match_eager_steps():
+    # Record 4 steps once, replay three times with eager work (moment and
+    # population read-backs, an eager step of another run) between the replays;
+    # every replay must leave the same state as eager stepping.
+    from paper_2504_15574_amd import Ensemble
+    specs = [(32, 64), (48, 96), (16, 32)]
+    g = _runs("f32", specs, seed=3)
+    e = _runs("f32", specs, seed=3)
+    other = _runs("f32", [(24, 48)], seed=4)[0]
+    ens_g, ens_e = Ensemble(g), Ensemble(e)
+    ens_g.capture(4)
+    for rep in range(3):
+        ens_g.replay()
+        ens_e.step(4)
+        other.step(1)
+        _ = g[0].moments()
+        for x, y in zip(g, e):
+            assert np.array_equal(x.populations(), y.populations()), f"replay {rep}"
+    ens_g.release()
+    for s in g + e + [other]:
+        s.close()
+
+
+def test_batch_argument_errors():
+    from paper_2504_15574_amd import VlbmError, vlbm_step_batch
+    a = _runs("f32", [(16, 32)], seed=5)[0]
+    b = _runs("f64", [(16, 32)], seed=5)[0]
+    with pytest.raises(VlbmError):
+        vlbm_step_batch([a.ctx, b.ctx], 1)          # mixed storage formats
+    with pytest.raises(VlbmError):
+        vlbm_step_batch([a.ctx, a.ctx], 1)          # the same run twice
+    with pytest.raises(VlbmError):
+        vlbm_step_batch([], 1)
+    a.close()
+    b.close()
+
+
+def test_shock_state_parity_with_oracle():
+    # The ensemble's initial state: rho = 1.5, T = 1.2 inside theta0, at rest
+    # (temperature enters through the order-3 projection); WENO meets the jump.
+    from paper_2504_15574_amd import Solver
+    nt, nph, tau = 64, 128, 2e-3
+    st = W.shock_state(nt, nph, theta0=np.pi / 4)
+    dt = oracle.suggest_dt(nt, nph, tau)
+    s = Solver(nt, nph, tau, dt)
+    s.init_fields(*st)
+    s.step(20)
+    fg = s.populations()
+    s.close()
+    fr = oracle.step(oracle.init(*st), 20, tau=tau, dt=dt, threads=8)
+    assert np.abs(fg - fr).max() <= 1e-12 * np.abs(fr).max()
