@@ -134,6 +134,15 @@ vlbm_status vlbm_set_populations(vlbm_ctx* ctx, const double* f, int ptr_on_devi
  * n_phi = 1).  Returns 0 for invalid parameters. */
 double vlbm_suggest_dt(const vlbm_params* params);
 
+/* The FP32 nodes v[4] (ascending) and product weights w[16] (k = 4 k_theta +
+ * k_phi) that the FP32 and FP16 storage formats compute with.  They are the
+ * D2Q16 Gauss-Hermite rule (App. A) moved by at most 10 ulps so that, evaluated
+ * exactly on these FP32 values, sum w - 1 (residual[0]) and sum w v_theta^2 - 1
+ * (residual[1]) nearly vanish: plain rounding leaves 2e-8 and 4e-8, and the
+ * BGK term would then relax the momentum toward (1 + 4e-8) rho u.  Host only;
+ * needs no device.  Errors: VLBM_ERR_ARG (NULL pointer). */
+vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[2]);
+
 /* ---- ensembles (many independent runs per launch) ---- */
 
 typedef struct vlbm_graph vlbm_graph;

@@ -92,6 +92,8 @@ struct RunDesc {
     int nt, np;
     double dt, inv_tau, rho0, eps;
     double a, b;          // out = a g_n + b (g_in + dt L)
+    const uint32_t* ctr;  // completed steps (reduced-precision storage: dither phase)
+    uint32_t seq;         // 16 * (stage - 1)
 };
 
 // Kernel arguments of a stage launch over the tiles of up to MAXRUNS runs
@@ -147,6 +149,14 @@ struct StF32 {
     __device__ static void bst(rsrc_t r, uint32_t vo, uint32_t so, T v, float) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
     }
+    // store g + d rounded with a dither x * 2^-32 ulp(g), x in [-2^31, 2^31):
+    // ulp(g) = 2^(E - 150) for the biased exponent E of g (zero and subnormal g
+    // get a dither that underflows to zero)
+    __device__ static void bst_dither(rsrc_t r, uint32_t vo, uint32_t so, T g, T d, float x, float) {
+        const int E = (int)((__builtin_bit_cast(uint32_t, g) >> 23) & 0xffu);
+        const T v = g + (d + __builtin_ldexpf(x, E - 182));
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
 };
 struct StF16 {
     using S = _Float16;
@@ -162,6 +172,15 @@ struct StF16 {
     }
     __device__ static void bst(rsrc_t r, uint32_t vo, uint32_t so, T v, float sc) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)(v * sc)), r, vo, so, 0);
+    }
+    // the FP16 ulp of the scaled value y is 2^(E - 137) for biased FP32 exponent
+    // E >= 113 and 2^-24 below (FP16 subnormals); the dither is x * 2^-32 of it
+    __device__ static void bst_dither(rsrc_t r, uint32_t vo, uint32_t so, T g, T d, float x, float sc) {
+        const T y = (g + d) * sc;
+        int E = (int)((__builtin_bit_cast(uint32_t, y) >> 23) & 0xffu);
+        E = E < 113 ? 113 : E;
+        const T v = y + __builtin_ldexpf(x, E - 169);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vo, so, 0);
     }
 };
 
@@ -260,8 +279,14 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     // a single-run launch reads its run from the kernel arguments; a batched one
     // looks up the run this tile belongs to (uniform per workgroup)
     int run = 0;
-    if (BATCH)
-        while (A.tile_start[run + 1] <= tg) ++run;
+    if (BATCH) {                               // largest run with tile_start[run] <= tg
+        int hi = A.nruns - 1;
+        while (run < hi) {
+            const int mid = (run + hi + 1) >> 1;
+            if (A.tile_start[mid] <= tg) run = mid;
+            else hi = mid - 1;
+        }
+    }
     const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
     const int t = tg - A.tile_start[run];
     const int nt = D.nt, np = D.np;
@@ -344,7 +369,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const T dsth = dt * T(D.rows.inv_sdth[csc]);
     const T dsph = dt * T(D.rows.inv_sdph[csc]);
     const T dtcot = dt * T(D.rows.cot[csc]);
-    const T keep = T(1) - dt * T(D.inv_tau);
+    const T dti = dt * T(D.inv_tau);
     const T eps12 = T(12.0 * D.eps);
     const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
                                         : static_cast<const void*>(D.rest_f);
@@ -418,7 +443,10 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             const T gc = gself, Ft = Ftself, Fl = Flself;
             const T Fb = fth[fb][(cr + 1) * TQ + cc];
             const T Fr = fph[fb][cr * (TQ + 1) + cc + 1];
-            acc[k] += keep * gc + R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
+            // FP64 folds the BGK loss -g/tau in here; the float kernels form the
+            // whole collision term at the end (see the epilogue)
+            if constexpr (sizeof(T) == 8) acc[k] += (T(1) - dti) * gc + R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
+            else acc[k] += R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
             const T tg = dtcot * gc;
 #pragma unroll
             for (int a = 0; a < NQ; ++a) {
@@ -446,20 +474,58 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const T irho = T(1) / rho;
     const T ut = jt * irho, up = jp * irho;
     const T u2 = ut * ut + up * up;
-    const T dti = dt * T(D.inv_tau);
     const T ca = T(D.a), cb = T(D.b);
     const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
     const rsrc_t rout = make_rsrc(D.out, NK * planeB);
     const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
+    if constexpr (sizeof(T) == 8) {
+        // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        const T vt = C.v[k >> 2], vp = C.v[k & 3];
-        const T xi = vt * ut + vp * up;
-        const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
-        const T y = acc[k] + dti * C.wk[k] * (drho + rho * pm1);
-        T o = cb * y;
-        if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
-        St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
+        for (int k = 0; k < NK; ++k) {
+            const T vt = C.v[k >> 2], vp = C.v[k & 3];
+            const T xi = vt * ut + vp * up;
+            const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
+            const T y = acc[k] + dti * C.wk[k] * (drho + rho * pm1);
+            T o = cb * y;
+            if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+            St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
+        }
+    } else {
+        // float kernels.  A reduced-precision store adds, every stage, nearly the
+        // same increment to nearly the same value: rounding to nearest then makes
+        // nearly the same error every step, and those errors add up coherently
+        // (linear instead of square-root growth in the number of steps).  Two
+        // measures keep the error at rounding level:
+        //  - the register sums hold only the increment dt L (the stage input g is
+        //    re-read here), so the arithmetic rounds at the scale of the
+        //    increment, and g + increment is rounded once;
+        //  - that one rounding is dithered: a value uniform in [-1/2, 1/2) ulp is
+        //    added before rounding to nearest, which makes the rounding unbiased
+        //    (stochastic rounding).  The dither of population k is h + k c mod
+        //    2^32 (c = 2^32 (sqrt5 - 1)/2, a Weyl step), where h is a 32-bit hash
+        //    (the "lowbias32" xorshift-multiply mixer) of the cell index, the
+        //    step counter and the stage.  A dither shared by all cells would
+        //    resonate with cells whose per-step increment matches its own step.
+        //    It depends on the step count only, so batched, single and
+        //    graph-replayed steps give identical bits.
+        uint32_t hsh = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) ^
+                       (*D.ctr * 0x9E3779B9u + D.seq * 0x85EBCA6Bu);
+        hsh ^= hsh >> 16; hsh *= 0x7feb352du;
+        hsh ^= hsh >> 15; hsh *= 0x846ca68bu;
+        hsh ^= hsh >> 16;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const T g = St::bld(rin, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+            const T vt = C.v[k >> 2], vp = C.v[k & 3];
+            const T xi = vt * ut + vp * up;
+            const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
+            const T inc = acc[k] + dti * (C.wk[k] * (drho + rho * pm1) - g);
+            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]
+            T d = cb * inc;
+            if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
+            const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
+            St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
+        }
     }
 }
 
@@ -656,6 +722,92 @@ double hermite(int n, double x) {
     return b;
 }
 
+// ---------------------------------------------------------------------------
+// FP32 quadrature for the float kernels.  Rounded to FP32, the nodes and
+// weights of the D2Q16 rule miss the identities sum w = 1 and sum w v^2 = 1
+// (App. A) by about 2e-8 and 4e-8.  The BGK term then relaxes the momentum toward
+// (1 + 4e-8) rho u instead of rho u: a small force along u that acts every step
+// and adds up over t / tau relaxation times.  Instead the FP32 nodes v_o =
+// sqrt(3 + sqrt6), v_i = sqrt(3 - sqrt6) and the class weights w_oo, w_oi, w_ii
+// of the product rule are moved by a few ulps, to the values within 10 ulps
+// (w_ii: the nearest floats to the mass identity) for which the two identities,
+// evaluated exactly on the FP32 values, hold best: among the candidates with
+// |sum w - 1| <= 2e-9 the one with the smallest |sum w v^2 - 1|, ties broken
+// by the fewest ulps moved.  Exact arithmetic: every product of three floats
+// is an integer multiple of 2^-100 below 2^127.
+namespace quad32 {
+constexpr int FXS = 100;
+using i128 = __int128;
+i128 exact(float a, float b = 1.f, float c = 1.f) {
+    const float f[3] = {a, b, c};
+    i128 m = 1;
+    int q = 0;
+    for (float x : f) {
+        int e;
+        const float fr = std::frexp(x, &e);
+        m *= (i128)(int64_t)std::ldexp(fr, 24);
+        q += e - 24;
+    }
+    const int sh = q + FXS;               // >= 0 for the magnitudes used here
+    return m * ((i128)1 << sh);
+}
+float step_ulps(float x, int n) {
+    for (int i = 0; i < (n < 0 ? -n : n); ++i) x = std::nextafter(x, n > 0 ? INFINITY : -INFINITY);
+    return x;
+}
+double to_d(i128 x) { return std::ldexp((double)x, -FXS); }
+struct Rule {
+    float vo, vi, woo, woi, wii;
+    double e00, e20;
+};
+Rule search() {
+    const double r6 = std::sqrt(6.0);
+    const double vo = std::sqrt(3.0 + r6), vi = std::sqrt(3.0 - r6);
+    const double h5o = vo * vo * vo * vo * vo - 10 * vo * vo * vo + 15 * vo;
+    const double h5i = vi * vi * vi * vi * vi - 10 * vi * vi * vi + 15 * vi;
+    const double wo = 24.0 / (h5o * h5o), wi = 24.0 / (h5i * h5i);
+    const i128 one = (i128)1 << FXS, lim00 = (i128)(2e-9 * std::ldexp(1.0, FXS));
+    constexpr int KU = 10;
+    Rule best{};
+    i128 best20 = -1;
+    int bestmove = 0;
+    for (int a = -KU; a <= KU; ++a) {
+        const float fvo = step_ulps((float)vo, a);
+        for (int b = -KU; b <= KU; ++b) {
+            const float fvi = step_ulps((float)vi, b);
+            for (int c = -KU; c <= KU; ++c) {
+                const float woo = step_ulps((float)(wo * wo), c);
+                for (int d = -KU; d <= KU; ++d) {
+                    const float woi = step_ulps((float)(wo * wi), d);
+                    const float c0 = (float)((1.0 - 4.0 * (double)woo - 8.0 * (double)woi) / 4.0);
+                    for (int e = -1; e <= 1; ++e) {
+                        const float wii = step_ulps(c0, e);
+                        const i128 e00 = 4 * exact(woo) + 8 * exact(woi) + 4 * exact(wii) - one;
+                        if (e00 > lim00 || -e00 > lim00) continue;
+                        i128 e20 = 4 * (exact(woo, fvo, fvo) + exact(woi, fvo, fvo) +
+                                        exact(woi, fvi, fvi) + exact(wii, fvi, fvi)) - one;
+                        if (e20 < 0) e20 = -e20;
+                        const int move = std::abs(a) + std::abs(b) + std::abs(c) + std::abs(d);
+                        if (best20 < 0 || e20 < best20 || (e20 == best20 && move < bestmove)) {
+                            best20 = e20;
+                            bestmove = move;
+                            best = Rule{fvo, fvi, woo, woi, wii, to_d(e00), 0.0};
+                            best.e20 = to_d(4 * (exact(woo, fvo, fvo) + exact(woi, fvo, fvo) +
+                                                 exact(woi, fvi, fvi) + exact(wii, fvi, fvi)) - one);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return best;
+}
+const Rule& rule() {
+    static const Rule r = search();
+    return r;
+}
+}  // namespace quad32
+
 void build_consts(Consts& c, int storage) {
     const double r6 = std::sqrt(6.0);
     c.v[0] = -std::sqrt(3.0 + r6);
@@ -765,7 +917,7 @@ size_t store_bytes(int storage) {
 constexpr int RED_BLOCKS = 1024;
 
 struct Layout {
-    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, fields, part, dout, desc, total;
+    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, fields, part, dout, desc, ctr, total;
 };
 
 Layout layout_of(const vlbm_params& p) {
@@ -785,6 +937,7 @@ Layout layout_of(const vlbm_params& p) {
     L.part = off; off += align_up(sizeof(double) * 8 * RED_BLOCKS);
     L.dout = off; off += align_up(sizeof(double) * 8);
     L.desc = off; off += align_up(sizeof(RunDesc) * 3);
+    L.ctr = off; off += align_up(sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -885,6 +1038,8 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
         D.rho0 = x->p.rho0;
         D.eps = x->p.weno_eps;
         D.gn = fn;
+        D.ctr = at<uint32_t>(x, x->L.ctr);
+        D.seq = 16u * (uint32_t)i;
     }
     d[0].gin = fn; d[0].out = fa; d[0].a = 0.0;       d[0].b = 1.0;
     d[1].gin = fa; d[1].out = fb; d[1].a = 0.75;      d[1].b = 0.25;
@@ -925,6 +1080,29 @@ vlbm_status launch_stage(vlbm_ctx* const* xs, int n, int stage, hipStream_t stre
     return VLBM_OK;
 }
 
+// Advance the step counters (dither phase of the reduced-precision stores) of
+// the contexts of one launch group, after their third stage.
+struct CtrArgs {
+    uint32_t* p[MAXRUNS];
+    int n;
+};
+__global__ __launch_bounds__(64) void count_step_kernel(CtrArgs a) {
+    const int i = threadIdx.x;
+    if (i < a.n) a.p[i][0] += 1u;
+}
+
+vlbm_status count_steps(vlbm_ctx* const* xs, int n, hipStream_t stream) {
+    for (int c0 = 0; c0 < n; c0 += MAXRUNS) {
+        CtrArgs a{};
+        a.n = n - c0 < MAXRUNS ? n - c0 : MAXRUNS;
+        for (int i = 0; i < a.n; ++i) a.p[i] = at<uint32_t>(xs[c0 + i], xs[c0 + i]->L.ctr);
+        hipLaunchKernelGGL(count_step_kernel, dim3(1), dim3(64), 0, stream, a);
+        vlbm_status st = launch_check();
+        if (st) return st;
+    }
+    return VLBM_OK;
+}
+
 vlbm_status check_batch(vlbm_ctx* const* xs, int n) {
     if (!xs || n < 1) return fail(VLBM_ERR_ARG, "empty context list");
     for (int i = 0; i < n; ++i) {
@@ -942,13 +1120,18 @@ vlbm_status check_batch(vlbm_ctx* const* xs, int n) {
 }
 
 vlbm_status step_batch(vlbm_ctx* const* xs, int n, int64_t n_steps, hipStream_t stream) {
-    for (int64_t i = 0; i < n_steps; ++i)
+    for (int64_t i = 0; i < n_steps; ++i) {
         for (int stage = 1; stage <= 3; ++stage) {
             vlbm_status st = dispatch(xs[0]->p.storage, [&](auto tag) {
                 return launch_stage<decltype(tag)>(xs, n, stage, stream);
             });
             if (st) return st;
         }
+        if (xs[0]->p.storage != VLBM_STORE_F64) {
+            vlbm_status st = count_steps(xs, n, stream);
+            if (st) return st;
+        }
+    }
     return VLBM_OK;
 }
 
@@ -979,6 +1162,19 @@ double vlbm_suggest_dt(const vlbm_params* p) {
     return dt;
 }
 
+vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[2]) {
+    if (!v || !w || !residual) return fail(VLBM_ERR_ARG, "NULL output");
+    const quad32::Rule& q = quad32::rule();
+    const float fv[NQ] = {-q.vo, -q.vi, q.vi, q.vo};
+    const float fw[3] = {q.woo, q.woi, q.wii};
+    for (int i = 0; i < NQ; ++i) v[i] = fv[i];
+    for (int k = 0; k < NK; ++k)
+        w[k] = fw[(int)((k >> 2) == 1 || (k >> 2) == 2) + (int)((k & 3) == 1 || (k & 3) == 2)];
+    residual[0] = q.e00;
+    residual[1] = q.e20;
+    return VLBM_OK;
+}
+
 vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
                         size_t workspace_bytes, vlbm_ctx** out) {
     g_err[0] = 0;
@@ -997,10 +1193,14 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     x->L = L;
     x->launches = 0;
     build_consts(x->c, p->storage);
-    for (int i = 0; i < NQ; ++i) { x->cd.v[i] = x->c.v[i]; x->cf.v[i] = (float)x->c.v[i]; }
+    const quad32::Rule& q32 = quad32::rule();
+    const float fv[NQ] = {-q32.vo, -q32.vi, q32.vi, q32.vo};
+    const float fw[3] = {q32.woo, q32.woi, q32.wii};   // by the number of inner nodes of k
+    for (int i = 0; i < NQ; ++i) { x->cd.v[i] = x->c.v[i]; x->cf.v[i] = fv[i]; }
     for (int k = 0; k < NK; ++k) {
         const double vw = x->c.v[k >> 2] * x->c.wk[k];
-        x->cd.wk[k] = x->c.wk[k]; x->cf.wk[k] = (float)x->c.wk[k];
+        const int inner = (int)((k >> 2) == 1 || (k >> 2) == 2) + (int)((k & 3) == 1 || (k & 3) == 2);
+        x->cd.wk[k] = x->c.wk[k]; x->cf.wk[k] = fw[inner];
         x->cd.vw[k] = vw; x->cf.vw[k] = (float)vw;
         x->cd.scale[k] = x->c.scale[k]; x->cf.scale[k] = (float)x->c.scale[k];
         x->cd.iscale[k] = x->c.iscale[k]; x->cf.iscale[k] = (float)x->c.iscale[k];
@@ -1026,8 +1226,11 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
                            hipMemcpyHostToDevice, x->stream);
     RunDesc descs[3];
     fill_descs(x, descs);
+    const uint32_t zero = 0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(x->ws + L.desc, descs, sizeof(descs), hipMemcpyHostToDevice, x->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(x->ws + L.ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, x->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
     if (e != hipSuccess) {
         delete x;

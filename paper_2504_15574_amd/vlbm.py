@@ -57,6 +57,7 @@ SIGNATURES = [
     ("vlbm_set_populations", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     ("vlbm_suggest_dt", ctypes.c_double, [_P]),
     ("vlbm_stage_launches", ctypes.c_int64, [_vp]),
+    ("vlbm_quadrature_f32", ctypes.c_int, [_vp, _vp, _dp]),
     ("vlbm_step_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64]),
     ("vlbm_graph_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
                                          ctypes.POINTER(_vp)]),
@@ -106,6 +107,17 @@ def vlbm_workspace_bytes(p: vlbm_params) -> int:
 
 def vlbm_suggest_dt(p: vlbm_params) -> float:
     return float(load().vlbm_suggest_dt(ctypes.byref(p)))
+
+
+def vlbm_quadrature_f32():
+    """FP32 nodes (4), product weights (16) and the residuals of sum w = 1 and
+    sum w v_theta^2 = 1 on those FP32 values."""
+    v = np.zeros(4, np.float32)
+    w = np.zeros(16, np.float32)
+    r = np.zeros(2)
+    _check(load().vlbm_quadrature_f32(v.ctypes.data, w.ctypes.data, r.ctypes.data_as(_dp)),
+           "vlbm_quadrature_f32")
+    return v, w, r
 
 
 def vlbm_create(p: vlbm_params, stream: int, workspace: int, nbytes: int) -> int:
@@ -264,36 +276,80 @@ class Solver:
 
 
 class Ensemble:
-    """Independent runs advanced together: one stage launch per RK stage covers
-    every run (``vlbm_step_batch``), optionally replayed from a HIP graph of
-    ``graph_steps`` steps.  Runs may differ in grid, tau and dt; they share the
-    storage format and torch's current stream."""
+    """Independent runs advanced together (``vlbm_step_batch``).
 
-    def __init__(self, solvers):
+    Runs may differ in grid, tau and dt; they share the storage format and the
+    stream.  ``grouping`` decides how runs are split into launches: ``"all"``
+    (one launch per RK stage for everything, 64 runs per launch), ``"by_size"``
+    (one launch per distinct grid) or ``"single"`` (one launch per run).  The
+    grouping never changes a cell's arithmetic, so every choice gives the same
+    bits; ``autotune`` picks the fastest.  ``capture``/``replay`` record and
+    replay a fixed number of steps as HIP graphs (one per group)."""
+
+    GROUPINGS = ("all", "by_size", "single")
+
+    def __init__(self, solvers, grouping="all"):
         self.solvers = list(solvers)
-        self.ctxs = [s.ctx for s in self.solvers]
-        self.graph = None
+        self.graphs = []
         self.graph_steps = 0
+        self.set_grouping(grouping)
+
+    def set_grouping(self, grouping):
+        if grouping not in self.GROUPINGS:
+            raise ValueError(grouping)
+        self.release()
+        self.grouping = grouping
+        if grouping == "all":
+            groups = [self.solvers]
+        elif grouping == "single":
+            groups = [[s] for s in self.solvers]
+        else:
+            by = {}
+            for s in self.solvers:
+                by.setdefault((s.n_theta, s.n_phi), []).append(s)
+            groups = list(by.values())
+        self.groups = [[s.ctx for s in g] for g in groups]
 
     def step(self, n=1):
-        vlbm_step_batch(self.ctxs, n)
+        for g in self.groups:
+            vlbm_step_batch(g, n)
         for s in self.solvers:
             s.t += n * s.dt
 
     def capture(self, steps):
         self.release()
-        self.graph = vlbm_graph_create(self.ctxs, steps)
+        self.graphs = [vlbm_graph_create(g, steps) for g in self.groups]
         self.graph_steps = steps
 
     def replay(self):
-        vlbm_graph_launch(self.graph)
+        for g in self.graphs:
+            vlbm_graph_launch(g)
         for s in self.solvers:
             s.t += self.graph_steps * s.dt
 
     def release(self):
-        if self.graph:
-            vlbm_graph_destroy(self.graph)
-            self.graph = None
+        for g in self.graphs:
+            vlbm_graph_destroy(g)
+        self.graphs = []
+
+    def autotune(self, steps=10, candidates=GROUPINGS):
+        """Time ``steps`` eager steps per grouping (this advances the runs) and
+        keep the fastest; returns {grouping: ms per step}."""
+        import torch
+        times = {}
+        for c in candidates:
+            self.set_grouping(c)
+            self.step(1)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(self.solvers[0].stream)
+            self.step(steps)
+            e1.record(self.solvers[0].stream)
+            torch.cuda.synchronize()
+            times[c] = e0.elapsed_time(e1) / steps
+        self.set_grouping(min(times, key=times.get))
+        return times
 
     def __del__(self):
         try:

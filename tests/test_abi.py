@@ -92,3 +92,29 @@ def test_missing_library_fails_loudly(tmp_path):
             B.load(str(tmp_path / "nope.so"))
     finally:
         B._lib = saved
+
+
+def test_fp32_quadrature_keeps_mass_and_momentum_identities(lib):
+    # The reduced-precision kernels compute with FP32 nodes and weights moved by
+    # a few ulps from the D2Q16 rule (App. A) so that the identities that make
+    # BGK conserve mass and momentum hold on the FP32 values themselves.  Checked
+    # here in exact rational arithmetic against the oracle's FP64 rule.
+    from fractions import Fraction as Fr
+    import numpy as np
+    v, w, r = B.vlbm_quadrature_f32()
+    v64, w1 = oracle.quadrature()
+    w64 = np.outer(w1, w1).ravel()
+    ulp = lambda x: np.spacing(np.float32(abs(x)))
+    assert np.all(np.abs(v.astype(np.float64) - v64) <= 10 * np.array([ulp(x) for x in v64]))
+    assert np.all(np.abs(w.astype(np.float64) - w64) <= 12 * np.array([ulp(x) for x in w64]))
+    assert np.array_equal(v, -v[::-1])                          # symmetric nodes
+    W = w.reshape(4, 4)
+    assert np.array_equal(W, W.T) and np.array_equal(W, W[::-1, ::-1])
+    m0 = sum(Fr(float(x)) for x in w) - 1
+    m2 = sum(Fr(float(w[4 * a + b])) * Fr(float(v[a])) ** 2 for a in range(4) for b in range(4)) - 1
+    assert abs(float(m0)) <= 2e-9 and float(m0) == r[0]
+    assert abs(float(m2)) <= 2e-10 and float(m2) == r[1]
+    # plain rounding of the FP64 rule misses the momentum identity by far more
+    vr, wr = v64.astype(np.float32), w64.astype(np.float32)
+    m2r = sum(Fr(float(wr[4 * a + b])) * Fr(float(vr[a])) ** 2 for a in range(4) for b in range(4)) - 1
+    assert abs(float(m2r)) > 100 * abs(float(m2))
