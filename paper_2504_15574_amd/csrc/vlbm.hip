@@ -377,8 +377,9 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const uint32_t rvo = (uint32_t)csc * (uint32_t)sizeof(T);
 
     T acc[NK];
+    T gk[NK];   // the cell's stage input, kept for the float epilogue
 #pragma unroll
-    for (int k = 0; k < NK; ++k) acc[k] = T(0);
+    for (int k = 0; k < NK; ++k) { acc[k] = T(0); gk[k] = T(0); }
     T drho = T(0), jt = T(0), jp = T(0);
 
     // Ring of three LDS slots: population p lives in slot p % 3.  Its global
@@ -453,6 +454,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
                 acc[a * NQ + kp] += C.fa[(kp * NQ + a) * NQ + kt] * tg;
                 acc[kt * NQ + a] += C.fb[(kt * NQ + a) * NQ + kp] * tg;
             }
+            if constexpr (sizeof(T) != 8) gk[k] = gc;
             drho += gc;
             jt += C.v[kt] * gc;
             jp += C.v[kp] * gc;
@@ -496,9 +498,9 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         // nearly the same error every step, and those errors add up coherently
         // (linear instead of square-root growth in the number of steps).  Two
         // measures keep the error at rounding level:
-        //  - the register sums hold only the increment dt L (the stage input g is
-        //    re-read here), so the arithmetic rounds at the scale of the
-        //    increment, and g + increment is rounded once;
+        //  - the register sums hold only the increment dt L (the stage input g of
+        //    the cell is kept aside in registers), so the arithmetic rounds at the
+        //    scale of the increment, and g + increment is rounded once;
         //  - that one rounding is dithered: a value uniform in [-1/2, 1/2) ulp is
         //    added before rounding to nearest, which makes the rounding unbiased
         //    (stochastic rounding).  The dither of population k is h + k c mod
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         hsh ^= hsh >> 16;
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-            const T g = St::bld(rin, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+            const T g = gk[k];
             const T vt = C.v[k >> 2], vp = C.v[k & 3];
             const T xi = vt * ut + vp * up;
             const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
