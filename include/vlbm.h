@@ -128,6 +128,13 @@ vlbm_status vlbm_get_populations(vlbm_ctx* ctx, double* f, int ptr_on_device);
 /* Encode FP64 populations [16][n_theta][n_phi] into f_n (checkpoint resume). */
 vlbm_status vlbm_set_populations(vlbm_ctx* ctx, const double* f, int ptr_on_device);
 
+/* Moment correction (used by the learned closure): in every cell, with rho, u
+ * the current moments, f_k += f^eq_k(rho + d_rho, u + d_u) - f^eq_k(rho, u)
+ * (isothermal order-3 equilibrium, eq. (feq_Q=4)); the non-equilibrium part of
+ * f is kept.  Fields as described above. */
+vlbm_status vlbm_correct_moments(vlbm_ctx* ctx, const double* d_rho, const double* d_u_theta,
+                                 const double* d_u_phi, int ptr_on_device);
+
 /* Largest stable time step suggested for these parameters: the smallest of
  * 0.2 dth, tau (explicit BGK needs dt < tau, Sec. V) and half the phi-CFL limit
  * of the row next to the pole, 0.5 R sin(dth/2) dph / v_max (dropped when

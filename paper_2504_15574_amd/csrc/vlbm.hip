@@ -582,6 +582,38 @@ template <class St>
 __device__ __forceinline__ void cell_moments(const typename St::S* in, size_t i, size_t n,
                                              const Consts& c, double rho0, double& rho,
                                              double& ut, double& up, double& T, double& e,
+                                             int& nbad);
+
+// Moment correction: f_k += f^eq_k(rho + d_rho, u + d_u) - f^eq_k(rho, u) with
+// the isothermal order-3 equilibrium (eq. (feq_Q=4)); the non-equilibrium part
+// of f is kept.
+template <class St>
+__global__ void correct_kernel(void* io, const double* drho, const double* dut, const double* dup,
+                               Consts c, int n, double rho0) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    typename St::S* f = static_cast<typename St::S*>(io);
+    double r, a, b, t, e;
+    int nb;
+    cell_moments<St>(f, i, n, c, rho0, r, a, b, t, e, nb);
+    const double r2 = r + drho[i], a2 = a + dut[i], b2 = b + dup[i];
+    const double u2 = a * a + b * b, w2 = a2 * a2 + b2 * b2;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const double vt = c.v[k >> 2], vp = c.v[k & 3];
+        const double x1 = vt * a + vp * b, x2 = vt * a2 + vp * b2;
+        const double p1 = x1 + 0.5 * (x1 * x1 - u2) + x1 * (x1 * x1 - 3.0 * u2) / 6.0;
+        const double p2 = x2 + 0.5 * (x2 * x2 - w2) + x2 * (x2 * x2 - 3.0 * w2) / 6.0;
+        const size_t o = (size_t)k * n + i;
+        const double g = (double)St::ld(f, o, c.iscale[k]) + c.wk[k] * ((r2 - r) + r2 * p2 - r * p1);
+        St::st(f, o, (typename St::T)g, c.scale[k]);
+    }
+}
+
+template <class St>
+__device__ __forceinline__ void cell_moments(const typename St::S* in, size_t i, size_t n,
+                                             const Consts& c, double rho0, double& rho,
+                                             double& ut, double& up, double& T, double& e,
                                              int& nbad) {
     double g[NK];
     double dr = 0, jt = 0, jp = 0;
@@ -1145,6 +1177,11 @@ vlbm_status copy_in(vlbm_ctx* x, double* dst, const double* src, size_t n, int o
 
 }  // namespace
 
+// error text shared with closure.hip (not exported)
+__attribute__((visibility("hidden"))) vlbm_status vlbm_set_error(vlbm_status st, const char* msg) {
+    return fail(st, "%s", msg);
+}
+
 extern "C" {
 
 size_t vlbm_workspace_bytes(const vlbm_params* p) {
@@ -1357,6 +1394,30 @@ vlbm_status vlbm_moments(vlbm_ctx* x, double* rho, double* ut, double* up, doubl
         if (T) HIP_OK(hipMemcpyAsync(T, dT, n * sizeof(double), hipMemcpyDeviceToHost, x->stream));
         HIP_OK(hipStreamSynchronize(x->stream));
     }
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_correct_moments(vlbm_ctx* x, const double* drho, const double* dut,
+                                 const double* dup, int on_dev) {
+    if (!x || !drho || !dut || !dup) return fail(VLBM_ERR_ARG, "NULL argument");
+    const int n = n_cells(x);
+    double* F = at<double>(x, x->L.fields);
+    const double *dr = drho, *da = dut, *db = dup;
+    if (!on_dev) {
+        HIP_OK(hipMemcpyAsync(F, drho, n * sizeof(double), hipMemcpyHostToDevice, x->stream));
+        HIP_OK(hipMemcpyAsync(F + n, dut, n * sizeof(double), hipMemcpyHostToDevice, x->stream));
+        HIP_OK(hipMemcpyAsync(F + 2 * (size_t)n, dup, n * sizeof(double), hipMemcpyHostToDevice, x->stream));
+        dr = F; da = F + n; db = F + 2 * (size_t)n;
+    }
+    void* fn = x->ws + x->L.fbuf[0];
+    vlbm_status st = dispatch(x->p.storage, [&](auto tag) {
+        using St = decltype(tag);
+        hipLaunchKernelGGL(correct_kernel<St>, dim3((n + 255) / 256), dim3(256), 0, x->stream,
+                           fn, dr, da, db, x->c, n, x->p.rho0);
+        return launch_check();
+    });
+    if (st) return st;
+    if (!on_dev) HIP_OK(hipStreamSynchronize(x->stream));
     return VLBM_OK;
 }
 

@@ -58,6 +58,7 @@ SIGNATURES = [
     ("vlbm_suggest_dt", ctypes.c_double, [_P]),
     ("vlbm_stage_launches", ctypes.c_int64, [_vp]),
     ("vlbm_quadrature_f32", ctypes.c_int, [_vp, _vp, _dp]),
+    ("vlbm_correct_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int]),
     ("vlbm_step_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64]),
     ("vlbm_graph_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
                                          ctypes.POINTER(_vp)]),
@@ -139,6 +140,11 @@ def vlbm_step(ctx, n: int):
 def vlbm_moments(ctx, rho, ut, up, T, on_device: int):
     _check(load().vlbm_moments(_vp(ctx), _vp(rho), _vp(ut), _vp(up), _vp(T), on_device),
            "vlbm_moments")
+
+
+def vlbm_correct_moments(ctx, drho, dut, dup, on_device: int):
+    _check(load().vlbm_correct_moments(_vp(ctx), _vp(drho), _vp(dut), _vp(dup), on_device),
+           "vlbm_correct_moments")
 
 
 def vlbm_destroy(ctx):
@@ -259,6 +265,14 @@ class Solver:
         f, ptr = _host(f)
         assert f.shape == (16, self.n_theta, self.n_phi)
         vlbm_set_populations(self.ctx, ptr, 0)
+
+    def correct_moments(self, drho, dut, dup):
+        """Add (d_rho, d_u) to the moments through the equilibrium (host fields)."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (drho, dut, dup)]
+        for a in arrs:
+            assert a.shape == (self.n_theta, self.n_phi)
+        vlbm_correct_moments(self.ctx, arrs[0].ctypes.data, arrs[1].ctypes.data,
+                             arrs[2].ctypes.data, 0)
 
     def diagnostics(self, raise_unstable=True):
         return vlbm_diagnostics(self.ctx, raise_unstable)

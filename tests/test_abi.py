@@ -14,12 +14,15 @@ from paper_2504_15574_amd import vlbm as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "vlbm.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("vlbm.h", "vlbm_closure.h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(vlbm_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(vlbm_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +40,8 @@ def test_header_declares_the_boundary():
 
 
 def test_every_declared_symbol_is_exported_and_bound(lib):
-    bound = {name for name, _, _ in B.SIGNATURES}
+    from paper_2504_15574_amd import closure
+    bound = {name for name, _, _ in B.SIGNATURES} | {name for name, _, _ in closure.SIGNATURES}
     for name in _declared():
         assert hasattr(lib, name), name
         assert name in bound, name
