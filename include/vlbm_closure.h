@@ -99,6 +99,13 @@ vlbm_status vlbm_clo_pack_input(vlbm_clo* c, int batch, const double* rho, const
 vlbm_status vlbm_clo_unpack_output(vlbm_clo* c, int batch, const float* z, double o_rho,
                                    double o_u, double* d_rho, double* d_u_theta, double* d_u_phi);
 
+/* Training target from two sets of moment fields (a: reference, b: prediction):
+ * target[p] = ((rho_a - rho_b) / o_rho, (u_theta_a - u_theta_b) / o_u,
+ * (u_phi_a - u_phi_b) / o_u) as FP32 [P][3]. */
+vlbm_status vlbm_clo_pack_target(vlbm_clo* c, int batch, const double* rho_a, const double* ut_a,
+                                 const double* up_a, const double* rho_b, const double* ut_b,
+                                 const double* up_b, double o_rho, double o_u, float* target);
+
 /* Coarse graining of fine FP64 fields [batch][n_theta_f][n_phi_f] by boxes of
  * factor x factor cells, with the area weight sin(theta): rho by area average,
  * u by momentum average (sum w rho u / sum w rho).  Needs no context. */

@@ -31,6 +31,7 @@ SIGNATURES = [
     ("vlbm_clo_pack_weights", _i, [_vp, _i, _i, _vp, _vp, _vp]),
     ("vlbm_clo_pack_input", _i, [_vp, _i, _vp, _vp, _vp, _d, _d, _vp]),
     ("vlbm_clo_unpack_output", _i, [_vp, _i, _vp, _d, _d, _vp, _vp, _vp]),
+    ("vlbm_clo_pack_target", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),
     ("vlbm_box_filter", _i, [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
 ]
 
@@ -196,6 +197,11 @@ class ClosureNet:
                 _ck(L.vlbm_clo_adam(self.ctx, p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v),
                                     self.step_count, lr, beta1, beta2, eps), "vlbm_clo_adam")
         self._pack()
+
+    def pack_target(self, batch, a, b, o_rho, o_u, target):
+        """target = (a - b) / (o_rho, o_u, o_u) from (rho, u_theta, u_phi) field triples."""
+        _ck(lib().vlbm_clo_pack_target(self.ctx, batch, *[_ptr(t) for t in a], *[_ptr(t) for t in b],
+                                       float(o_rho), float(o_u), _ptr(target)), "vlbm_clo_pack_target")
 
     def unpack_output(self, batch, o_rho, o_u, drho, dut, dup):
         _ck(lib().vlbm_clo_unpack_output(self.ctx, batch, _ptr(self.z[2]), float(o_rho), float(o_u),

@@ -348,6 +348,17 @@ __global__ void unpack_output_kernel(int P, const float* __restrict__ z, double 
     dup[p] = (double)z[(size_t)p * 16 + 2] * o_u;
 }
 
+__global__ void pack_target_kernel(int P, const double* __restrict__ ra, const double* __restrict__ ua,
+                                   const double* __restrict__ va, const double* __restrict__ rb,
+                                   const double* __restrict__ ub, const double* __restrict__ vb,
+                                   double i_rho, double i_u, float* __restrict__ t) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    t[(size_t)p * 3] = (float)((ra[p] - rb[p]) * i_rho);
+    t[(size_t)p * 3 + 1] = (float)((ua[p] - ub[p]) * i_u);
+    t[(size_t)p * 3 + 2] = (float)((va[p] - vb[p]) * i_u);
+}
+
 __global__ void box_filter_kernel(int Hf, int Wf, int f, int n, const double* __restrict__ rho,
                                   const double* __restrict__ ut, const double* __restrict__ up,
                                   double* __restrict__ rc, double* __restrict__ uc,
@@ -625,6 +636,18 @@ vlbm_status vlbm_clo_unpack_output(vlbm_clo* c, int batch, const float* z, doubl
     const int P = c->H * c->W * batch;
     hipLaunchKernelGGL(unpack_output_kernel, dim3((P + 255) / 256), dim3(256), 0, c->stream, P, z,
                        o_rho, o_u, dr, dut, dup);
+    return launched();
+}
+
+vlbm_status vlbm_clo_pack_target(vlbm_clo* c, int batch, const double* ra, const double* ua,
+                                 const double* va, const double* rb, const double* ub,
+                                 const double* vb, double o_rho, double o_u, float* t) {
+    if (vlbm_status st = check_batch(c, batch)) return st;
+    if (!ra || !ua || !va || !rb || !ub || !vb || !t) return err(VLBM_ERR_ARG, "NULL tensor");
+    if (!(o_rho > 0) || !(o_u > 0)) return err(VLBM_ERR_ARG, "output scales must be > 0");
+    const int P = c->H * c->W * batch;
+    hipLaunchKernelGGL(pack_target_kernel, dim3((P + 255) / 256), dim3(256), 0, c->stream, P, ra, ua,
+                       va, rb, ub, vb, 1.0 / o_rho, 1.0 / o_u, t);
     return launched();
 }
 

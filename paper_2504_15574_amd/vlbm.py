@@ -200,6 +200,13 @@ def vlbm_graph_destroy(graph):
 
 
 # ---- convenience object ---------------------------------------------------------
+def _dptr(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise VlbmError("expected a contiguous float64 device tensor")
+    return t.data_ptr()
+
+
 def _host(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data
@@ -243,6 +250,20 @@ class Solver:
     def step(self, n=1):
         vlbm_step(self.ctx, n)
         self.t += n * self.dt
+
+    # fields already in device memory: contiguous FP64 torch tensors [n_theta, n_phi]
+    def init_fields_device(self, rho, ut, up):
+        vlbm_init_fields(self.ctx, _dptr(rho), _dptr(ut), _dptr(up), None, 1)
+        self.t = 0.0
+
+    def moments_device(self, rho, ut, up):
+        vlbm_moments(self.ctx, _dptr(rho), _dptr(ut), _dptr(up), None, 1)
+
+    def vorticity_device(self, omega):
+        vlbm_vorticity(self.ctx, _dptr(omega), 1)
+
+    def correct_moments_device(self, drho, dut, dup):
+        vlbm_correct_moments(self.ctx, _dptr(drho), _dptr(dut), _dptr(dup), 1)
 
     def moments(self, with_T=True):
         shape = (self.n_theta, self.n_phi)
