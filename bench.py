@@ -112,7 +112,7 @@ def run_ensemble(steps):
     shock (rho = 1.5, T = 1.2 for theta < theta0, theta0 uniform in [pi/6, pi/3])
     per run, seed 0 (draws (nu, theta0) in run order); dt per run from the
     stability rule.  Times `steps` steps one run at a time, batched, and batched
-    from a HIP graph after the grouping autotuner."""
+    from a HIP graph after the autotuner (launch grouping x tile shape)."""
     import torch
     import workloads as W
     from paper_2504_15574_amd import Ensemble, Solver
@@ -167,6 +167,7 @@ def run_ensemble(steps):
     mlups = lambda ms: round(cells * steps / (ms * 1e-3) / 1e6, 1)
     return {"workload": "64 shock runs: 32 x 128x256 + 32 x 256x512, D2Q16, f32 deviation store",
             "steps": steps, "cells": cells, "grouping": ens.grouping,
+            "tile": f"{ens.tile[0]}x{ens.tile[1]}",
             "autotune_ms_per_step": {k: round(v, 4) for k, v in tune.items()},
             "mlups_one_run_per_launch": mlups(one), "mlups_batched": mlups(bat),
             "mlups_batched_graph": mlups(gr), "finite": finite}
@@ -185,6 +186,28 @@ def cpu_baseline(state, threads):
                       f"FP64 plain-C oracle, OpenMP over theta rows, {el:.1f} s wall"}
 
 
+def run_closure():
+    """Learned closure (coarse 32x64 FP32 + 3x3 CNN vs fine 256x512 runs filtered
+    8x): 32 training seeds, 8 held-out seeds, 40 closure intervals of 25 coarse
+    steps (t = 0.2).  Reports errors against the filtered fine run at the last
+    interval and the cost of each run per unit simulated time."""
+    from paper_2504_15574_amd.closure_train import Config, run
+    cfg = Config()
+    r = run(cfg, log=lambda s: print("[bench]" + s, file=sys.stderr, flush=True))
+    last = lambda name, key: round(r[name]["errors"][key][-1][1], 5)
+    out = {"workload": "decaying turbulence, coarse 32x64 FP32 (+closure) vs fine 256x512 FP32 "
+                       "filtered 8x; 32 training / 8 held-out seeds, t = 0.2",
+           "train_loss_first_last": [round(x, 4) for x in r["loss_first_last"]]}
+    for name in ("coarse", "closure"):
+        out[name] = {"vorticity_rel_l2": last(name, "vorticity"), "u_rel_l2": last(name, "u"),
+                     "vorticity_spectrum_mean_abs_log10": last(name, "spectrum_dex"),
+                     "ms_device_per_unit_time_per_run": round(r[name]["ms_per_unit_time_per_run"], 2),
+                     "cost_ratio_fine_over_this": round(r[name]["cost_ratio_fine_over_this"], 1)}
+    out["fine_ms_device_per_unit_time_per_run"] = round(r["fine_ms_per_unit_time_per_run"], 1)
+    out["wall_s"] = round(r["wall_s"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +220,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-run batched-ensemble measurement")
     ap.add_argument("--ensemble-steps", type=int, default=400)
+    ap.add_argument("--no-closure", action="store_true",
+                    help="skip the learned-closure experiment (training and evaluation, ~20 s)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times); "
                          "calibrates the HBM byte counters against a known traffic")
@@ -296,6 +321,12 @@ def main():
         print("[bench] batched ensemble ...", file=sys.stderr, flush=True)
         out["ensemble"] = run_ensemble(args.ensemble_steps)
         print(f"[bench] ensemble: {out['ensemble']}", file=sys.stderr, flush=True)
+
+    if not args.no_closure:
+        print("[bench] learned closure: fine data, training, evaluation ...", file=sys.stderr,
+              flush=True)
+        out["closure"] = run_closure()
+        print(f"[bench] closure: {out['closure']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))

@@ -176,6 +176,12 @@ vlbm_status vlbm_graph_launch(vlbm_graph* graph);
 /* Release the graph (not the contexts). */
 vlbm_status vlbm_graph_destroy(vlbm_graph* graph);
 
+/* Tile shape (theta rows x phi columns) of the context's stage launches: 15 x 16
+ * (the default) or 7 x 32.  The shape never changes a cell's arithmetic, so
+ * every choice gives the same bits; contexts of one batch must share it.
+ * Errors: VLBM_ERR_ARG (NULL), VLBM_ERR_UNSUPPORTED (other shapes). */
+vlbm_status vlbm_set_tile_shape(vlbm_ctx* ctx, int rows, int cols);
+
 /* Number of stage-kernel launches issued so far by this context (a batched
  * launch counts once for every context it covers). */
 int64_t vlbm_stage_launches(const vlbm_ctx* ctx);

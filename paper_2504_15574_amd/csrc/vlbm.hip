@@ -249,19 +249,33 @@ __device__ __forceinline__ int wrap(int q, int np) {
 // Workgroups are numbered so that those sharing an XCD (dispatched round-robin
 // over the 8 XCDs) take a contiguous range of tiles, keeping halo rows and the
 // 64-byte halves of shared cache lines inside one L2.
-constexpr int TS = 15, TQ = 16, NTHR = 256;
-constexpr int LR = TS + 2 * NGH, LC = TQ + 2 * NGH, LT = LR * LC;   // 21 x 22
-constexpr int NLOAD = LR * TQ + TS * 2 * NGH;                       // 426 cross-shaped values
-constexpr int NFT = (TS + 1) * TQ;                                  // 256 theta interfaces
-constexpr int NFP = TS * (TQ + 1);                                  // 255 phi interfaces
-static_assert(NFT == NTHR && NFP <= NTHR && NLOAD <= 2 * NTHR && TS * TQ <= NTHR, "tile shape");
+// Two tile shapes fit this thread mapping ((TS + 1) TQ theta interfaces = 256
+// threads, at most two cross-shaped loads per thread): 15 x 16 (the default,
+// least halo per cell) and 7 x 32 (fewer rows, for grids whose row count 15
+// divides badly).  Neither changes any cell's arithmetic.
+constexpr int NTHR = 256;
+template <int TS_, int TQ_>
+struct TileShape {
+    static constexpr int TS = TS_, TQ = TQ_;
+    static constexpr int LR = TS + 2 * NGH, LC = TQ + 2 * NGH, LT = LR * LC;
+    static constexpr int NLOAD = LR * TQ + TS * 2 * NGH;       // cross-shaped values
+    static constexpr int NFT = (TS + 1) * TQ;                  // theta interfaces
+    static constexpr int NFP = TS * (TQ + 1);                  // phi interfaces
+    static_assert(NFT == NTHR && NFP <= NTHR && NLOAD <= 2 * NTHR && TS * TQ <= NTHR, "tile shape");
+};
+using Tile15x16 = TileShape<15, 16>;
+using Tile7x32 = TileShape<7, 32>;
+constexpr int TILE_ROWS[2] = {15, 7}, TILE_COLS[2] = {16, 32};
 
-__host__ __device__ inline int n_tiles(int nt, int np) {
-    return ((nt + TS - 1) / TS) * ((np + TQ - 1) / TQ);
+__host__ __device__ inline int n_tiles(int nt, int np, int shape) {
+    const int ts = shape ? 7 : 15, tq = shape ? 32 : 16;
+    return ((nt + ts - 1) / ts) * ((np + tq - 1) / tq);
 }
 
-template <class St, bool BATCH>
+template <class St, bool BATCH, class Tl>
 __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
+    constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, LC = Tl::LC, LT = Tl::LT;
+    constexpr int NLOAD = Tl::NLOAD, NFT = Tl::NFT, NFP = Tl::NFP;
     using T = typename St::T;
     constexpr int B = St::B;
     constexpr int PAD = 8;                     // destination of the unused load slots
@@ -1012,6 +1026,7 @@ struct vlbm_ctx {
     ConstsT<float> cf;
     int64_t launches;
     int device;
+    int tile;       // 0: 15 x 16 tiles, 1: 7 x 32
 };
 
 struct vlbm_graph {
@@ -1094,19 +1109,21 @@ vlbm_status launch_stage(vlbm_ctx* const* xs, int n, int stage, hipStream_t stre
         for (int i = 0; i < m; ++i) {
             vlbm_ctx* x = xs[c0 + i];
             A.desc[i] = desc_of(x, stage);
-            A.tile_start[i + 1] = A.tile_start[i] + n_tiles(x->p.n_theta, x->p.n_phi);
+            A.tile_start[i + 1] = A.tile_start[i] + n_tiles(x->p.n_theta, x->p.n_phi, x->tile);
             x->launches++;
         }
         const int nb = A.tile_start[m];
+        const dim3 grid(8 * ((nb + 7) / 8));
+        const bool wide = xs[c0]->tile == 1;
         if (m == 1) {
             RunDesc d[3];
             fill_descs(xs[c0], d);
             A.run0 = d[stage - 1];
-            hipLaunchKernelGGL((stage_kernel<St, false>), dim3(8 * ((nb + 7) / 8)), dim3(NTHR), 0,
-                               stream, A);
+            if (wide) hipLaunchKernelGGL((stage_kernel<St, false, Tile7x32>), grid, dim3(NTHR), 0, stream, A);
+            else hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16>), grid, dim3(NTHR), 0, stream, A);
         } else {
-            hipLaunchKernelGGL((stage_kernel<St, true>), dim3(8 * ((nb + 7) / 8)), dim3(NTHR), 0,
-                               stream, A);
+            if (wide) hipLaunchKernelGGL((stage_kernel<St, true, Tile7x32>), grid, dim3(NTHR), 0, stream, A);
+            else hipLaunchKernelGGL((stage_kernel<St, true, Tile15x16>), grid, dim3(NTHR), 0, stream, A);
         }
         vlbm_status st = launch_check();
         if (st) return st;
@@ -1147,6 +1164,8 @@ vlbm_status check_batch(vlbm_ctx* const* xs, int n) {
             return fail(VLBM_ERR_ARG, "contexts of a batch must share the stream");
         if (xs[i]->device != xs[0]->device)
             return fail(VLBM_ERR_ARG, "contexts of a batch must share the device");
+        if (xs[i]->tile != xs[0]->tile)
+            return fail(VLBM_ERR_ARG, "contexts of a batch must share the tile shape");
         for (int j = 0; j < i; ++j)
             if (xs[j] == xs[i]) return fail(VLBM_ERR_ARG, "context %d appears twice", i);
     }
@@ -1201,6 +1220,16 @@ double vlbm_suggest_dt(const vlbm_params* p) {
     return dt;
 }
 
+vlbm_status vlbm_set_tile_shape(vlbm_ctx* x, int rows, int cols) {
+    if (!x) return fail(VLBM_ERR_ARG, "NULL context");
+    for (int i = 0; i < 2; ++i)
+        if (rows == TILE_ROWS[i] && cols == TILE_COLS[i]) {
+            x->tile = i;
+            return VLBM_OK;
+        }
+    return fail(VLBM_ERR_UNSUPPORTED, "tile shape %dx%d (supported: 15x16, 7x32)", rows, cols);
+}
+
 vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[2]) {
     if (!v || !w || !residual) return fail(VLBM_ERR_ARG, "NULL output");
     const quad32::Rule& q = quad32::rule();
@@ -1231,6 +1260,7 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     x->ws = static_cast<char*>(workspace);
     x->L = L;
     x->launches = 0;
+    x->tile = 0;
     build_consts(x->c, p->storage);
     const quad32::Rule& q32 = quad32::rule();
     const float fv[NQ] = {-q32.vo, -q32.vi, q32.vi, q32.vo};

@@ -59,6 +59,7 @@ SIGNATURES = [
     ("vlbm_stage_launches", ctypes.c_int64, [_vp]),
     ("vlbm_quadrature_f32", ctypes.c_int, [_vp, _vp, _dp]),
     ("vlbm_correct_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int]),
+    ("vlbm_set_tile_shape", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     ("vlbm_step_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64]),
     ("vlbm_graph_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
                                          ctypes.POINTER(_vp)]),
@@ -145,6 +146,10 @@ def vlbm_moments(ctx, rho, ut, up, T, on_device: int):
 def vlbm_correct_moments(ctx, drho, dut, dup, on_device: int):
     _check(load().vlbm_correct_moments(_vp(ctx), _vp(drho), _vp(dut), _vp(dup), on_device),
            "vlbm_correct_moments")
+
+
+def vlbm_set_tile_shape(ctx, rows: int, cols: int):
+    _check(load().vlbm_set_tile_shape(_vp(ctx), int(rows), int(cols)), "vlbm_set_tile_shape")
 
 
 def vlbm_destroy(ctx):
@@ -314,25 +319,37 @@ class Ensemble:
     """Independent runs advanced together (``vlbm_step_batch``).
 
     Runs may differ in grid, tau and dt; they share the storage format and the
-    stream.  ``grouping`` decides how runs are split into launches: ``"all"``
-    (one launch per RK stage for everything, 64 runs per launch), ``"by_size"``
-    (one launch per distinct grid) or ``"single"`` (one launch per run).  The
-    grouping never changes a cell's arithmetic, so every choice gives the same
-    bits; ``autotune`` picks the fastest.  ``capture``/``replay`` record and
-    replay a fixed number of steps as HIP graphs (one per group)."""
+    stream.  Two launch parameters never change a cell's arithmetic, so every
+    choice gives the same bits: ``grouping`` splits the runs into launches
+    (``"all"``: one launch per RK stage for everything, 64 runs per launch;
+    ``"by_size"``: one launch per distinct grid; ``"single"``: one launch per
+    run) and ``tile`` is the stage kernel's tile shape (15 x 16 or 7 x 32,
+    rows x columns).  ``autotune`` times the combinations and keeps the
+    fastest.  ``capture``/``replay`` record and replay a fixed number of steps
+    as HIP graphs (one per launch group)."""
 
     GROUPINGS = ("all", "by_size", "single")
+    TILES = ((15, 16), (7, 32))
 
-    def __init__(self, solvers, grouping="all"):
+    def __init__(self, solvers, grouping="all", tile=(15, 16)):
         self.solvers = list(solvers)
         self.graphs = []
         self.graph_steps = 0
-        self.set_grouping(grouping)
+        self.tile = None
+        self.configure(grouping, tile)
 
-    def set_grouping(self, grouping):
+    def configure(self, grouping=None, tile=None):
+        grouping = self.grouping if grouping is None else grouping
+        tile = self.tile if tile is None else tuple(tile)
         if grouping not in self.GROUPINGS:
             raise ValueError(grouping)
+        if tile not in self.TILES:
+            raise ValueError(tile)
         self.release()
+        if tile != self.tile:
+            for s in self.solvers:
+                vlbm_set_tile_shape(s.ctx, *tile)
+            self.tile = tile
         self.grouping = grouping
         if grouping == "all":
             groups = [self.solvers]
@@ -344,6 +361,9 @@ class Ensemble:
                 by.setdefault((s.n_theta, s.n_phi), []).append(s)
             groups = list(by.values())
         self.groups = [[s.ctx for s in g] for g in groups]
+
+    def set_grouping(self, grouping):
+        self.configure(grouping=grouping)
 
     def step(self, n=1):
         for g in self.groups:
@@ -367,24 +387,27 @@ class Ensemble:
             vlbm_graph_destroy(g)
         self.graphs = []
 
-    def autotune(self, steps=10, candidates=GROUPINGS):
-        """Time ``steps`` eager steps per grouping (this advances the runs) and
-        keep the fastest; returns {grouping: ms per step}."""
+    def autotune(self, steps=10, groupings=GROUPINGS, tiles=TILES):
+        """Time ``steps`` eager steps per (grouping, tile) combination (this
+        advances the runs) and keep the fastest; returns
+        {"grouping/rowsxcols": ms per step}."""
         import torch
         times = {}
-        for c in candidates:
-            self.set_grouping(c)
-            self.step(1)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(self.solvers[0].stream)
-            self.step(steps)
-            e1.record(self.solvers[0].stream)
-            torch.cuda.synchronize()
-            times[c] = e0.elapsed_time(e1) / steps
-        self.set_grouping(min(times, key=times.get))
-        return times
+        for t in tiles:
+            for c in groupings:
+                self.configure(c, t)
+                self.step(1)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(self.solvers[0].stream)
+                self.step(steps)
+                e1.record(self.solvers[0].stream)
+                torch.cuda.synchronize()
+                times[(c, t)] = e0.elapsed_time(e1) / steps
+        best = min(times, key=times.get)
+        self.configure(*best)
+        return {f"{c}/{t[0]}x{t[1]}": v for (c, t), v in times.items()}
 
     def __del__(self):
         try:

@@ -121,3 +121,49 @@ def test_shock_state_parity_with_oracle():
     s.close()
     fr = oracle.step(oracle.init(*st), 20, tau=tau, dt=dt, threads=8)
     assert np.abs(fg - fr).max() <= 1e-12 * np.abs(fr).max()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_tile_shapes_give_identical_bits(storage):
+    # 7 x 32 tiles against the default 15 x 16, single and batched launches
+    from paper_2504_15574_amd import Ensemble
+    specs = [(26, 50), (37, 1), (32, 64), (20, 130)]
+    a = _runs(storage, specs, seed=11)
+    b = _runs(storage, specs, seed=11)
+    Ensemble(a, tile=(7, 32)).step(5)
+    for s in b:
+        s.step(5)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.populations(), y.populations())
+    for s in a + b:
+        s.close()
+
+
+def test_wide_tiles_match_the_oracle():
+    from paper_2504_15574_amd import Solver, vlbm_set_tile_shape
+    nt, nph, tau = 23, 70, 2e-3
+    st = W.random_state(nt, nph, seed=12, du=0.05, dT=0.05, smooth=False)
+    dt = oracle.suggest_dt(nt, nph, tau)
+    s = Solver(nt, nph, tau, dt)
+    vlbm_set_tile_shape(s.ctx, 7, 32)
+    s.init_fields(*st)
+    s.step(6)
+    fg = s.populations()
+    s.close()
+    fr = oracle.step(oracle.init(*st), 6, tau=tau, dt=dt, threads=8)
+    assert np.abs(fg - fr).max() <= 1e-12 * np.abs(fr).max()
+
+
+def test_tile_shape_errors_and_autotuner():
+    from paper_2504_15574_amd import Ensemble, VlbmError, vlbm_set_tile_shape, vlbm_step_batch
+    a, b = _runs("f32", [(16, 32), (16, 32)], seed=13)
+    with pytest.raises(VlbmError):
+        vlbm_set_tile_shape(a.ctx, 8, 32)
+    vlbm_set_tile_shape(a.ctx, 7, 32)
+    with pytest.raises(VlbmError):
+        vlbm_step_batch([a.ctx, b.ctx], 1)          # mixed tile shapes
+    ens = Ensemble([a, b])
+    times = ens.autotune(steps=2)
+    assert len(times) == 6 and ens.tile in Ensemble.TILES
+    a.close()
+    b.close()
