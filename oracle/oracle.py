@@ -48,11 +48,14 @@ def lib():
         L.or_force.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
         L.or_weno5.restype = ctypes.c_double
         L.or_weno5.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double]
-        L.or_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                             ctypes.c_double, _dp, _dp, _dp, _dp, ctypes.c_int]
-        L.or_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                              ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int64,
-                              ctypes.c_int, _dp]
+        L.or_flux.restype = ctypes.c_double
+        L.or_flux.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_double]
+        L.or_rhs_s.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp,
+                               ctypes.c_int]
+        L.or_step_s.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                _dp, ctypes.c_int64, ctypes.c_int, _dp]
         L.or_init.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.or_moments.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.or_vorticity.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
@@ -118,26 +121,41 @@ def weno5(h6, f6, direction, eps=1e-6):
     return lib().or_weno5(_p(h6), _p(f6), int(direction), eps)
 
 
-def rhs(f, R=1.0, tau=1e-3, eps=1e-6, threads=1, pole_fluxes=False):
+SCHEMES = {"weno5": 0, "u1": 1, "u2": 2, "u3": 3}
+
+
+def flux(scheme, h6, f6, direction, eps=1e-6):
+    """Interface flux of a scheme (eqs. (fluxes_U1-3), (fluxes_W5)) from the six
+    points s-2 .. s+3 around s+1/2."""
+    h6 = _arr(h6)
+    f6 = _arr(f6)
+    return lib().or_flux(SCHEMES[scheme], _p(h6), _p(f6), int(direction), eps)
+
+
+def rhs(f, R=1.0, tau=1e-3, eps=1e-6, threads=1, pole_fluxes=False, scheme="weno5",
+        komissarov=False):
     f = _arr(f)
     _, nt, np_ = f.shape
     L = np.zeros_like(f)
     fn = np.zeros((16, np_)) if pole_fluxes else None
     fs = np.zeros((16, np_)) if pole_fluxes else None
-    rc = lib().or_rhs(nt, np_, R, tau, eps, _p(f), _p(L), _p(fn), _p(fs), threads)
+    rc = lib().or_rhs_s(nt, np_, R, tau, eps, SCHEMES[scheme], int(komissarov), _p(f), _p(L),
+                        _p(fn), _p(fs), threads)
     if rc:
         raise ValueError("oracle rejected the grid")
     return (L, fn, fs) if pole_fluxes else L
 
 
-def step(f, nsteps, R=1.0, tau=1e-3, dt=1e-3, eps=1e-6, threads=1, budget=False):
+def step(f, nsteps, R=1.0, tau=1e-3, dt=1e-3, eps=1e-6, threads=1, budget=False,
+         scheme="weno5", komissarov=False):
     """Advance ``nsteps`` SSP-RK3 steps; returns the new populations (and the
-    pole-flux mass budget when ``budget``)."""
+    pole-flux mass budget when ``budget``).  ``scheme``: weno5, u1, u2, u3;
+    ``komissarov``: the theta derivative of eq. (Komissarov_scheme)."""
     f = _arr(f).copy()
     _, nt, np_ = f.shape
     b = np.zeros(1)
-    rc = lib().or_step(nt, np_, R, tau, dt, eps, _p(f), int(nsteps), threads,
-                       _p(b) if budget else None)
+    rc = lib().or_step_s(nt, np_, R, tau, dt, eps, SCHEMES[scheme], int(komissarov), _p(f),
+                         int(nsteps), threads, _p(b) if budget else None)
     if rc:
         raise ValueError("oracle rejected the grid")
     return (f, float(b[0])) if budget else f

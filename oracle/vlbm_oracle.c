@@ -15,7 +15,10 @@
  *               (kernels).
  *   Sec. III.D  cell-centred grid, eq. (discrete_coord_sphere).
  *   Sec. III.E  flux-form advection, eq. (discrete_advection_sphere); WENO-5
- *               fluxes, eqs. (fluxes_W5), (WENO5_delta), (WENO5_sigma).
+ *               fluxes, eqs. (fluxes_W5), (WENO5_delta), (WENO5_sigma); the
+ *               upwind fluxes U1, U2, U3, eq. (fluxes_U1-3); the "Komissarov"
+ *               form of the theta derivative, eqs. (Komissarov_scheme),
+ *               (Komissarov_sin_cos).
  *   Sec. III.F  periodic phi ghosts, eq. (bcs_phi); pole ghosts, eq.
  *               (bcs_theta).
  *   Sec. III.G  SSP-RK3 and the operator L[f], eq. (Lf).
@@ -50,6 +53,9 @@
 #define NV 4            /* Q, nodes per axis */
 #define NK 16           /* Q*Q populations */
 #define NG 3            /* ghost layers: the WENO-5 stencil reaches 3 cells */
+
+/* advection schemes (Sec. III.E) */
+enum { OR_WENO5 = 0, OR_U1 = 1, OR_U2 = 2, OR_U3 = 3 };
 
 int or_version(void) { return 1; }
 
@@ -230,6 +236,26 @@ double or_weno5(const double h6[6], const double f6[6], int dir, double eps)
     return weno5_pos(hm, fm, eps);
 }
 
+/* Eq. (fluxes_U1-3) for a positive velocity from the points s-1, s, s+1 of
+ * the interface s+1/2 (h already holds V f):
+ *   U1: h_s;  U2: 3/2 h_s - 1/2 h_{s-1};  U3: 1/3 h_{s+1} + 5/6 h_s - 1/6 h_{s-1}. */
+static double upwind_pos(int scheme, double hm1, double h0, double hp1)
+{
+    switch (scheme) {
+    case OR_U1: return h0;
+    case OR_U2: return 1.5 * h0 - 0.5 * hm1;
+    default: return hp1 / 3.0 + 5.0 * h0 / 6.0 - hm1 / 6.0;
+    }
+}
+
+/* Interface flux of any scheme from the six points s-2 .. s+3 (as or_weno5). */
+double or_flux(int scheme, const double h6[6], const double f6[6], int dir, double eps)
+{
+    if (scheme == OR_WENO5) return or_weno5(h6, f6, dir, eps);
+    if (dir > 0) return upwind_pos(scheme, h6[1], h6[2], h6[3]);
+    return upwind_pos(scheme, h6[4], h6[3], h6[2]);   /* mirror: s+m -> s+1-m */
+}
+
 /* ---------------------------------------------------------------------- */
 /* Ghost-extended copy of one population set, Sec. III.F.                   */
 typedef struct {
@@ -275,9 +301,16 @@ static void fill_ghosts(const double* f, ext_t* x)
 /* Eq. (Lf) on the whole grid.
  *   L_k = -[ (F^th_{s+1/2} - F^th_{s-1/2})/dth + (F^ph_{q+1/2} - F^ph_{q-1/2})/dph ] / (R sin th_s)
  *         + G_k (inertial force) + C_k (BGK)
+ * with the theta flux function V f = v sin(theta_j) f_j.  With komissarov != 0
+ * the theta part is eq. (Komissarov_scheme) instead:
+ *   [F^th_{s+1/2} sin th_{s+1/2} - F^th_{s-1/2} sin th_{s-1/2}] / (R (cos th_{s-1/2} - cos th_{s+1/2}))
+ * with V f = v f_j and the interface angles of eq. (Komissarov_sin_cos)
+ * (0-based: th_{s+1/2} = (s+1) dth).
  * fn / fs (optional, [16][np]) receive the theta fluxes through the first
- * (north, s = -1/2) and last (south, s = nt-1/2) interfaces.               */
-static int rhs_ext(int nt, int np, double R, double tau, double eps,
+ * (north, s = -1/2) and last (south, s = nt-1/2) interfaces, as they enter the
+ * theta difference (times sin th_{-1/2} = 0 and sin th_{nt-1/2} = 0 for the
+ * Komissarov form).                                                        */
+static int rhs_ext(int nt, int np, double R, double tau, double eps, int scheme, int komissarov,
                    const double* f, double* L, double* fn, double* fs, int nthreads)
 {
     tables();
@@ -304,11 +337,15 @@ static int rhs_ext(int nt, int np, double R, double tau, double eps,
             for (int q = 0; q < np; ++q) {
                 for (int m = 0; m < 6; ++m) {
                     int j = s - 2 + m;
-                    double sj = sin((j + 0.5) * dth);   /* signed in ghost rows */
+                    double sj = komissarov ? 1.0 : sin((j + 0.5) * dth);   /* signed in ghost rows */
                     f6[m] = *E(&x, k, j, q);
                     h6[m] = vk * sj * f6[m];
                 }
-                Ft[((size_t)k * (nt + 1) + (s + 1)) * np + q] = or_weno5(h6, f6, dir, eps);
+                double F = or_flux(scheme, h6, f6, dir, eps);
+                /* sin th_{s+1/2} = sin((s+1) dth), written as the sine of the
+                 * angle to the nearer pole so that both pole values are 0 */
+                if (komissarov) F *= sin((s + 1 < nt - (s + 1) ? s + 1 : nt - (s + 1)) * dth);
+                Ft[((size_t)k * (nt + 1) + (s + 1)) * np + q] = F;
             }
         }
     }
@@ -324,7 +361,7 @@ static int rhs_ext(int nt, int np, double R, double tau, double eps,
                     f6[m] = *E(&x, k, s, q - 2 + m);
                     h6[m] = vk * f6[m];
                 }
-                Fp[((size_t)k * nt + s) * (np + 1) + (q + 1)] = or_weno5(h6, f6, dir, eps);
+                Fp[((size_t)k * nt + s) * (np + 1) + (q + 1)] = or_flux(scheme, h6, f6, dir, eps);
             }
         }
     }
@@ -333,6 +370,7 @@ static int rhs_ext(int nt, int np, double R, double tau, double eps,
     for (int s = 0; s < nt; ++s) {
         double th = (s + 0.5) * dth;
         double rs = R * sin(th);
+        double rk = R * (cos(s * dth) - cos((s + 1) * dth));   /* Komissarov band */
         double fc[NK], C[NK], G[NK];
         for (int q = 0; q < np; ++q) {
             for (int k = 0; k < NK; ++k) fc[k] = *E(&x, k, s, q);
@@ -343,7 +381,8 @@ static int rhs_ext(int nt, int np, double R, double tau, double eps,
                 double ftm = Ft[((size_t)k * (nt + 1) + s) * np + q];
                 double fpp = Fp[((size_t)k * nt + s) * (np + 1) + (q + 1)];
                 double fpm = Fp[((size_t)k * nt + s) * (np + 1) + q];
-                double adv = ((ftp - ftm) / dth + (fpp - fpm) / dph) / rs;
+                double adv = komissarov ? (ftp - ftm) / rk + (fpp - fpm) / (dph * rs)
+                                        : ((ftp - ftm) / dth + (fpp - fpm) / dph) / rs;
                 L[((size_t)k * nt + s) * np + q] = -adv + G[k] + C[k];
             }
         }
@@ -365,11 +404,17 @@ static int check_grid(int nt, int np)
     return 0;
 }
 
+int or_rhs_s(int nt, int np, double R, double tau, double eps, int scheme, int komissarov,
+             const double* f, double* L, double* flux_north, double* flux_south, int nthreads)
+{
+    if (check_grid(nt, np) || scheme < OR_WENO5 || scheme > OR_U3) return -1;
+    return rhs_ext(nt, np, R, tau, eps, scheme, komissarov, f, L, flux_north, flux_south, nthreads);
+}
+
 int or_rhs(int nt, int np, double R, double tau, double eps, const double* f,
            double* L, double* flux_north, double* flux_south, int nthreads)
 {
-    if (check_grid(nt, np)) return -1;
-    return rhs_ext(nt, np, R, tau, eps, f, L, flux_north, flux_south, nthreads);
+    return or_rhs_s(nt, np, R, tau, eps, OR_WENO5, 0, f, L, flux_north, flux_south, nthreads);
 }
 
 /* Sec. III.G: one SSP-RK3 step per iteration,
@@ -379,10 +424,10 @@ int or_rhs(int nt, int np, double R, double tau, double eps, const double* f,
  * budget (optional) accumulates, over the steps, the mass change that the
  * pole fluxes imply: dt * sum over stages with weights (1/6, 1/6, 2/3) of
  *   -R dph sum_{k,q} (F^th_{nt-1/2} - F^th_{-1/2}).                        */
-int or_step(int nt, int np, double R, double tau, double dt, double eps,
-            double* f, int64_t nsteps, int nthreads, double* budget)
+int or_step_s(int nt, int np, double R, double tau, double dt, double eps, int scheme,
+              int komissarov, double* f, int64_t nsteps, int nthreads, double* budget)
 {
-    if (check_grid(nt, np)) return -1;
+    if (check_grid(nt, np) || scheme < OR_WENO5 || scheme > OR_U3) return -1;
     size_t n = (size_t)NK * nt * np;
     double* L = (double*)malloc(sizeof(double) * n);
     double* f1 = (double*)malloc(sizeof(double) * n);
@@ -400,7 +445,7 @@ int or_step(int nt, int np, double R, double tau, double dt, double eps,
         double b[3] = {0.0, 0.0, 0.0};
         const double* in[3] = {f, f1, f2};
         for (int st = 0; st < 3 && rc == 0; ++st) {
-            rc = rhs_ext(nt, np, R, tau, eps, in[st], L, fn, fs, nthreads);
+            rc = rhs_ext(nt, np, R, tau, eps, scheme, komissarov, in[st], L, fn, fs, nthreads);
             if (rc) break;
             if (budget) {
                 double acc = 0.0;
@@ -422,6 +467,12 @@ int or_step(int nt, int np, double R, double tau, double dt, double eps,
     }
     free(L); free(f1); free(f2); free(fn); free(fs);
     return rc;
+}
+
+int or_step(int nt, int np, double R, double tau, double dt, double eps,
+            double* f, int64_t nsteps, int nthreads, double* budget)
+{
+    return or_step_s(nt, np, R, tau, dt, eps, OR_WENO5, 0, f, nsteps, nthreads, budget);
 }
 
 /* ---------------------------------------------------------------------- */
