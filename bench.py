@@ -186,6 +186,34 @@ def cpu_baseline(state, threads):
                       f"FP64 plain-C oracle, OpenMP over theta rows, {el:.1f} s wall"}
 
 
+def run_schemes(state, steps):
+    """Cost of the advection schemes on the benchmark grid: MLUPS of U1, U2, U3
+    and WENO-5, each in the standard and the Komissarov form, FP32 and FP64
+    deviation store, `steps` timed steps after 2 warm-up steps."""
+    import torch
+    from paper_2504_15574_amd import Solver
+    out = {}
+    for storage in ("f32", "f64"):
+        for scheme in ("u1", "u2", "u3", "weno5"):
+            for kom in (False, True):
+                sol = Solver(N_THETA, N_PHI, TAU, storage=storage, scheme=scheme, komissarov=kom)
+                sol.init_fields(*state)
+                sol.step(2)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(sol.stream)
+                sol.step(steps)
+                e1.record(sol.stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / steps
+                ok = sol.diagnostics(raise_unstable=False)[4] == 0
+                sol.close()
+                out[f"{storage}/{scheme}{'+komissarov' if kom else ''}"] = {
+                    "mlups": round(N_THETA * N_PHI / (ms * 1e-3) / 1e6, 1), "finite": bool(ok)}
+    return out
+
+
 def run_closure():
     """Learned closure (coarse 32x64 FP32 + 3x3 CNN vs fine 256x512 runs filtered
     8x): 32 training seeds, 8 held-out seeds, 40 closure intervals of 25 coarse
@@ -220,6 +248,9 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-run batched-ensemble measurement")
     ap.add_argument("--ensemble-steps", type=int, default=400)
+    ap.add_argument("--no-schemes", action="store_true",
+                    help="skip the advection-scheme cost comparison (U1/U2/U3/WENO-5, Komissarov)")
+    ap.add_argument("--scheme-steps", type=int, default=100)
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the learned-closure experiment (training and evaluation, ~20 s)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -321,6 +352,11 @@ def main():
         print("[bench] batched ensemble ...", file=sys.stderr, flush=True)
         out["ensemble"] = run_ensemble(args.ensemble_steps)
         print(f"[bench] ensemble: {out['ensemble']}", file=sys.stderr, flush=True)
+
+    if not args.no_schemes:
+        print("[bench] advection schemes ...", file=sys.stderr, flush=True)
+        out["schemes"] = run_schemes(state, args.scheme_steps)
+        print(f"[bench] schemes: {out['schemes']}", file=sys.stderr, flush=True)
 
     if not args.no_closure:
         print("[bench] learned closure: fine data, training, evaluation ...", file=sys.stderr,

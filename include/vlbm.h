@@ -54,8 +54,19 @@ typedef enum {
     VLBM_STORE_F16_DEV = 2   /* (f_k - w_k rho0) * 2^e_k stored in FP16, FP32 arithmetic */
 } vlbm_storage;
 
+/* Advection scheme (Sec. III.E): the interface flux in the low bits, optionally
+ * OR-ed with VLBM_ADV_KOMISSAROV for the theta derivative of eq.
+ * (Komissarov_scheme): flux function v f (no sin theta), interface flux times
+ * sin theta_{s+-1/2} (exactly 0 at the poles), divided by
+ * R (cos theta_{s-1/2} - cos theta_{s+1/2}); exactly well-balanced at rest and
+ * at most second order. */
 typedef enum {
-    VLBM_ADV_WENO5 = 0       /* WENO-5 fluxes, eqs. (fluxes_W5)-(WENO5_sigma) */
+    VLBM_ADV_WENO5 = 0,          /* WENO-5 fluxes, eqs. (fluxes_W5)-(WENO5_sigma) */
+    VLBM_ADV_U1 = 1,             /* first-order upwind, eq. (fluxes_U1-3)          */
+    VLBM_ADV_U2 = 2,             /* second-order upwind                            */
+    VLBM_ADV_U3 = 3,             /* third-order upwind                             */
+    VLBM_ADV_SCHEME_MASK = 0xff,
+    VLBM_ADV_KOMISSAROV = 0x100
 } vlbm_advection;
 
 /* Problem statement (Sec. III, Sec. IV): grid, quadrature, tau, dt, scheme. */
@@ -70,7 +81,7 @@ typedef struct {
     double rho0;           /* reference density of the stored deviations (> 0)       */
     double weno_eps;       /* > 0; nonlinear weights delta_j / (eps + sigma_j)^2     */
     int32_t storage;       /* vlbm_storage                                           */
-    int32_t advection;     /* vlbm_advection                                         */
+    int32_t advection;     /* vlbm_advection: scheme | optional VLBM_ADV_KOMISSAROV  */
 } vlbm_params;
 
 /* Bytes of device workspace a context with these parameters needs (0 when the

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/vlbm.h"
@@ -73,6 +74,7 @@ struct Rows {
     const double* cot;       // [nt]: cos th_s / (R sin th_s)
     const double* rest;      // [16][nt]: dt * L of the rest state w_k rho0 at central-candidate weights
     const double* dC;        // [2][nt + 1][2]: rho0 (C1 - C2), rho0 (C3 - C2) of sin th per interface
+    const double* sI;        // [nt + 1]: factor of the theta flux at interface i (Komissarov: sin th_{i-1/2})
 };
 
 // the constants the stage kernel uses, in its arithmetic type
@@ -94,6 +96,7 @@ struct RunDesc {
     double a, b;          // out = a g_n + b (g_in + dt L)
     const uint32_t* ctr;  // completed steps (reduced-precision storage: dither phase)
     uint32_t seq;         // 16 * (stage - 1)
+    int scheme;           // VLBM_ADV_WENO5 / U1 / U2 / U3
 };
 
 // Kernel arguments of a stage launch over the tiles of up to MAXRUNS runs
@@ -223,6 +226,16 @@ __device__ __forceinline__ T weno5(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g
     return F2 + r * (n1 * (d1 + c1) + n3 * (d3 + c3));
 }
 
+// Upwind fluxes U1, U2, U3 of eq. (fluxes_U1-3) from the stencil points in
+// upwind order (a = s-1, b = s, c = s+1 for a positive velocity; the mirror
+// s+2, s+1, s for a negative one).
+template <class T>
+__device__ __forceinline__ T upwind(int scheme, T a, T b, T c) {
+    if (scheme == VLBM_ADV_U1) return b;
+    if (scheme == VLBM_ADV_U2) return T(1.5) * b - T(0.5) * a;
+    return c * T(1.0 / 3.0) + b * T(5.0 / 6.0) - a * T(1.0 / 6.0);
+}
+
 template <class T> __device__ __forceinline__ const ConstsT<T>& consts_of(const StageArgs& A);
 template <> __device__ __forceinline__ const ConstsT<double>& consts_of<double>(const StageArgs& A) { return A.cd; }
 template <> __device__ __forceinline__ const ConstsT<float>& consts_of<float>(const StageArgs& A) { return A.cf; }
@@ -272,7 +285,10 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
     return ((nt + ts - 1) / ts) * ((np + tq - 1) / tq);
 }
 
-template <class St, bool BATCH, class Tl>
+// GEN: the general variant (any advection scheme, Komissarov interface factor),
+// launched when a run of the launch needs it; the default WENO-5 standard form
+// uses the specialised variant, which keeps two registers fewer.
+template <class St, bool BATCH, class Tl, bool GEN>
 __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, LC = Tl::LC, LT = Tl::LT;
     constexpr int NLOAD = Tl::NLOAD, NFT = Tl::NFT, NFP = Tl::NFP;
@@ -366,6 +382,8 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
     const T dCp1 = T(D.rows.dC[2 * ig]), dCp3 = T(D.rows.dC[2 * ig + 1]);
     const T dCm1 = T(D.rows.dC[2 * (nt + 1) + 2 * ig]), dCm3 = T(D.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
+    const T sIf = GEN ? T(D.rows.sI[ig]) : T(1);         // 1, or sin th at the interface (Komissarov)
+    const int scheme = GEN ? D.scheme : (int)VLBM_ADV_WENO5;
     // ---- phi interface of this thread: the left face of its cell for the 240
     // cell threads, the right faces of column 15 for threads 240..254
     const bool phas = tid < NFP;
@@ -431,12 +449,17 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             }
             gself = g[3];                                // this thread's cell (row ti, column tc)
             T F;
-            if (kt >= 2)
-                F = weno5(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4], eps12,
-                          vw * dCp1, vw * dCp3);
-            else
-                F = weno5(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1], eps12,
-                          vw * dCm1, vw * dCm3);
+            if (scheme == VLBM_ADV_WENO5) {
+                if (kt >= 2)
+                    F = weno5(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4], eps12,
+                              vw * dCp1, vw * dCp3);
+                else
+                    F = weno5(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1], eps12,
+                              vw * dCm1, vw * dCm3);
+            } else {
+                F = kt >= 2 ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
+            }
+            if constexpr (GEN) F *= sIf;
             fth[fb][tid] = F;
             Ftself = F;                                  // top face of this thread's cell
         }
@@ -446,10 +469,14 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 #pragma unroll
             for (int m = 0; m < 6; ++m) g[m] = tile[tb][pbase + m];
             T F;
-            if (kp >= 2)
-                F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
-            else
-                F = weno5(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1], eps12, T(0), T(0));
+            if (scheme == VLBM_ADV_WENO5) {
+                if (kp >= 2)
+                    F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
+                else
+                    F = weno5(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1], eps12, T(0), T(0));
+            } else {
+                F = kp >= 2 ? upwind(scheme, g[1], g[2], g[3]) : upwind(scheme, g[4], g[3], g[2]);
+            }
             Flself = C.v[kp] * F;                        // left face of this thread's cell
             fph[fb][pslot] = Flself;
         }
@@ -902,24 +929,35 @@ void build_consts(Consts& c, int storage) {
 // C2 part and the inertial force on w_k rho0 are exact per row and go into
 // rest[] (times dt); the kernel adds w1 (C1 - C2) + w3 (C3 - C2) from dC.
 struct HostRows {
-    std::vector<double> sinv, inv_sdth, inv_sdph, cot, rest, dC;
+    std::vector<double> sinv, inv_sdth, inv_sdph, cot, rest, dC, sI;
 };
 
 void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
     const int nt = p.n_theta, np = p.n_phi;
     const double dth = M_PI / nt, dph = 2.0 * M_PI / np, R = p.radius;
+    const int scheme = p.advection & VLBM_ADV_SCHEME_MASK;
+    const bool kom = (p.advection & VLBM_ADV_KOMISSAROV) != 0;
+    // theta flux function V f = v S_j f: S_j = sin th_j (signed in ghost rows), or
+    // 1 in the Komissarov form, eq. (Komissarov_scheme), whose interface flux is
+    // then multiplied by sin th_{i-1/2} (the angle to the nearer pole, so both
+    // pole values are 0) and divided by R (cos th_{s-1/2} - cos th_{s+1/2})
     h.sinv.resize(nt + 2 * NGH);
-    for (int j = -NGH; j < nt + NGH; ++j) h.sinv[j + NGH] = std::sin((j + 0.5) * dth);
+    for (int j = -NGH; j < nt + NGH; ++j) h.sinv[j + NGH] = kom ? 1.0 : std::sin((j + 0.5) * dth);
+    h.sI.resize(nt + 1);
+    for (int i = 0; i <= nt; ++i) h.sI[i] = kom ? std::sin((i < nt - i ? i : nt - i) * dth) : 1.0;
     h.inv_sdth.resize(nt);
     h.inv_sdph.resize(nt);
     h.cot.resize(nt);
     for (int s = 0; s < nt; ++s) {
         const double th = (s + 0.5) * dth;
-        h.inv_sdth[s] = 1.0 / (R * std::sin(th) * dth);
+        h.inv_sdth[s] = kom ? 1.0 / (R * (std::cos(s * dth) - std::cos((s + 1) * dth)))
+                            : 1.0 / (R * std::sin(th) * dth);
         h.inv_sdph[s] = 1.0 / (R * std::sin(th) * dph);
         h.cot[s] = std::cos(th) / (R * std::sin(th));
     }
-    // candidate reconstructions of S_j = sin th_j at interface i (= s + 1/2, s = i - 1)
+    // reconstructions of S_j at interface i (= s + 1/2, s = i - 1): the rest
+    // state's flux (WENO: central candidate C2, whose weights the kernel adds
+    // through C1 - C2 and C3 - C2; upwind schemes: their fixed stencil)
     h.dC.assign(2 * (nt + 1) * 2, 0.0);
     std::vector<double> c2(2 * (nt + 1));
     for (int dir = 0; dir < 2; ++dir)
@@ -930,12 +968,24 @@ void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
                 const int j = dir == 0 ? s - 2 + m : s + 3 - m;   // mirrored stencil
                 P[m] = h.sinv[j + NGH];
             }
-            const double C1 = P[0] / 3.0 - 7.0 * P[1] / 6.0 + 11.0 * P[2] / 6.0;
-            const double C2 = -P[1] / 6.0 + 5.0 * P[2] / 6.0 + P[3] / 3.0;
-            const double C3 = P[2] / 3.0 + 5.0 * P[3] / 6.0 - P[4] / 6.0;
-            h.dC[(dir * (nt + 1) + i) * 2 + 0] = p.rho0 * (C1 - C2);
-            h.dC[(dir * (nt + 1) + i) * 2 + 1] = p.rho0 * (C3 - C2);
-            c2[dir * (nt + 1) + i] = C2;
+            double rec;
+            if (kom) {
+                rec = 1.0;              // every scheme reconstructs a constant exactly
+            } else if (scheme == VLBM_ADV_WENO5) {
+                const double C1 = P[0] / 3.0 - 7.0 * P[1] / 6.0 + 11.0 * P[2] / 6.0;
+                const double C2 = -P[1] / 6.0 + 5.0 * P[2] / 6.0 + P[3] / 3.0;
+                const double C3 = P[2] / 3.0 + 5.0 * P[3] / 6.0 - P[4] / 6.0;
+                h.dC[(dir * (nt + 1) + i) * 2 + 0] = p.rho0 * (C1 - C2);
+                h.dC[(dir * (nt + 1) + i) * 2 + 1] = p.rho0 * (C3 - C2);
+                rec = C2;
+            } else if (scheme == VLBM_ADV_U1) {
+                rec = P[2];
+            } else if (scheme == VLBM_ADV_U2) {
+                rec = 1.5 * P[2] - 0.5 * P[1];
+            } else {
+                rec = P[3] / 3.0 + 5.0 * P[2] / 6.0 - P[1] / 6.0;
+            }
+            c2[dir * (nt + 1) + i] = rec * h.sI[i];
         }
     h.rest.assign((size_t)NK * nt, 0.0);
     const double r0 = p.rho0;
@@ -965,7 +1015,7 @@ size_t store_bytes(int storage) {
 constexpr int RED_BLOCKS = 1024;
 
 struct Layout {
-    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, fields, part, dout, desc, ctr, total;
+    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, sI, fields, part, dout, desc, ctr, total;
 };
 
 Layout layout_of(const vlbm_params& p) {
@@ -981,6 +1031,7 @@ Layout layout_of(const vlbm_params& p) {
     L.rest = off; off += align_up(sizeof(double) * NK * p.n_theta);
     L.rest_f = off; off += align_up(sizeof(float) * NK * p.n_theta);
     L.dC = off; off += align_up(sizeof(double) * 4 * (p.n_theta + 1));
+    L.sI = off; off += align_up(sizeof(double) * (p.n_theta + 1));
     L.fields = off; off += align_up(sizeof(double) * 4 * n);
     L.part = off; off += align_up(sizeof(double) * 8 * RED_BLOCKS);
     L.dout = off; off += align_up(sizeof(double) * 8);
@@ -1010,7 +1061,9 @@ vlbm_status check_params(const vlbm_params* p) {
         return fail(VLBM_ERR_ARG, "non-finite parameter");
     if (p->q != 4) return fail(VLBM_ERR_UNSUPPORTED, "only q = 4 (D2Q16) is implemented");
     if (p->storage < 0 || p->storage > 2) return fail(VLBM_ERR_UNSUPPORTED, "unknown storage %d", p->storage);
-    if (p->advection != VLBM_ADV_WENO5) return fail(VLBM_ERR_UNSUPPORTED, "unknown advection %d", p->advection);
+    if ((p->advection & ~(VLBM_ADV_SCHEME_MASK | VLBM_ADV_KOMISSAROV)) ||
+        (p->advection & VLBM_ADV_SCHEME_MASK) > VLBM_ADV_U3)
+        return fail(VLBM_ERR_UNSUPPORTED, "unknown advection %d", p->advection);
     return VLBM_OK;
 }
 
@@ -1079,6 +1132,8 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
         D.rows.cot = at<double>(x, x->L.cot);
         D.rows.rest = at<double>(x, x->L.rest);
         D.rows.dC = at<double>(x, x->L.dC);
+        D.rows.sI = at<double>(x, x->L.sI);
+        D.scheme = x->p.advection & VLBM_ADV_SCHEME_MASK;
         D.rest_f = at<float>(x, x->L.rest_f);
         D.nt = x->p.n_theta;
         D.np = x->p.n_phi;
@@ -1115,15 +1170,26 @@ vlbm_status launch_stage(vlbm_ctx* const* xs, int n, int stage, hipStream_t stre
         const int nb = A.tile_start[m];
         const dim3 grid(8 * ((nb + 7) / 8));
         const bool wide = xs[c0]->tile == 1;
+        bool gen = false;
+        for (int i = 0; i < m; ++i) gen = gen || xs[c0 + i]->p.advection != VLBM_ADV_WENO5;
         if (m == 1) {
             RunDesc d[3];
             fill_descs(xs[c0], d);
             A.run0 = d[stage - 1];
-            if (wide) hipLaunchKernelGGL((stage_kernel<St, false, Tile7x32>), grid, dim3(NTHR), 0, stream, A);
-            else hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16>), grid, dim3(NTHR), 0, stream, A);
+        }
+        // one of the 8 (single/batch x tile x general/specialised) instantiations
+        auto go = [&](auto batch, auto tl, auto g) {
+            hipLaunchKernelGGL((stage_kernel<St, decltype(batch)::value, decltype(tl), decltype(g)::value>),
+                               grid, dim3(NTHR), 0, stream, A);
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        if (m == 1) {
+            if (wide) { if (gen) go(F_{}, Tile7x32{}, T_{}); else go(F_{}, Tile7x32{}, F_{}); }
+            else { if (gen) go(F_{}, Tile15x16{}, T_{}); else go(F_{}, Tile15x16{}, F_{}); }
         } else {
-            if (wide) hipLaunchKernelGGL((stage_kernel<St, true, Tile7x32>), grid, dim3(NTHR), 0, stream, A);
-            else hipLaunchKernelGGL((stage_kernel<St, true, Tile15x16>), grid, dim3(NTHR), 0, stream, A);
+            if (wide) { if (gen) go(T_{}, Tile7x32{}, T_{}); else go(T_{}, Tile7x32{}, F_{}); }
+            else { if (gen) go(T_{}, Tile15x16{}, T_{}); else go(T_{}, Tile15x16{}, F_{}); }
         }
         vlbm_status st = launch_check();
         if (st) return st;
@@ -1284,7 +1350,7 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     hipError_t e = hipGetDevice(&x->device);
     const struct { size_t off; const std::vector<double>* v; } up[] = {
         {L.sinv, &h.sinv}, {L.inv_sdth, &h.inv_sdth}, {L.inv_sdph, &h.inv_sdph},
-        {L.cot, &h.cot}, {L.rest, &h.rest}, {L.dC, &h.dC}};
+        {L.cot, &h.cot}, {L.rest, &h.rest}, {L.dC, &h.dC}, {L.sI, &h.sI}};
     for (const auto& u : up) {
         if (e != hipSuccess) break;
         e = hipMemcpyAsync(x->ws + u.off, u.v->data(), u.v->size() * sizeof(double),

@@ -21,6 +21,8 @@ STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_ALLOC", 4: "ERR_DEVICE",
           5: "ERR_UNSTABLE"}
 ADV_WENO5 = 0
+ADVECTION = {"weno5": 0, "u1": 1, "u2": 2, "u3": 3}
+ADV_KOMISSAROV = 0x100
 
 # (name, restype, argtypes) of every symbol include/vlbm.h declares
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -97,9 +99,10 @@ def _check(st: int, what: str):
 
 
 def make_params(n_theta, n_phi, tau, dt, storage="f64", radius=1.0, rho0=1.0, weno_eps=1e-6,
-                q=4) -> vlbm_params:
+                q=4, scheme="weno5", komissarov=False) -> vlbm_params:
+    adv = ADVECTION[scheme] | (ADV_KOMISSAROV if komissarov else 0)
     return vlbm_params(ABI_VERSION, int(n_theta), int(n_phi), int(q), float(radius), float(tau),
-                       float(dt), float(rho0), float(weno_eps), STORAGE[storage], ADV_WENO5)
+                       float(dt), float(rho0), float(weno_eps), STORAGE[storage], adv)
 
 
 # ---- C-named wrappers (argument marshalling only) -------------------------------
@@ -224,13 +227,14 @@ class Solver:
     ``torch.cuda.current_stream()`` at construction (or ``stream``)."""
 
     def __init__(self, n_theta, n_phi, tau, dt=None, storage="f64", radius=1.0, rho0=1.0,
-                 weno_eps=1e-6, stream=None):
+                 weno_eps=1e-6, stream=None, scheme="weno5", komissarov=False):
         import torch
         if not torch.cuda.is_available():
             raise VlbmError("no HIP device visible to torch")
         load()
         self.n_theta, self.n_phi = int(n_theta), int(n_phi)
-        p = make_params(n_theta, n_phi, tau, 1.0, storage, radius, rho0, weno_eps)
+        p = make_params(n_theta, n_phi, tau, 1.0, storage, radius, rho0, weno_eps,
+                        scheme=scheme, komissarov=komissarov)
         if dt is None:
             dt = vlbm_suggest_dt(p)
         p.dt = float(dt)
