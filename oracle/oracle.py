@@ -1,9 +1,10 @@
 """ctypes binding of the plain-C FP64 vLBM oracle (``vlbm_oracle.c``).
 
 Test infrastructure only: see the package docstring.  Arrays are numpy
-float64, C-contiguous; populations are ``[16, n_theta, n_phi]`` with
-``k = 4*k_theta + k_phi`` over ascending Gauss-Hermite nodes, fields are
-``[n_theta, n_phi]``.
+float64, C-contiguous; populations are ``[Q*Q, n_theta, n_phi]`` with
+``k = Q*k_theta + k_phi`` over ascending Gauss-Hermite nodes (Q = 4: D2Q16, the
+default; Q = 3: D2Q9), fields are ``[n_theta, n_phi]``.  Functions that take
+populations infer Q from their count; the others take ``q``.
 """
 from __future__ import annotations
 
@@ -39,6 +40,7 @@ def lib():
     if _lib is None:
         build()
         L = ctypes.CDLL(_LIB)
+        L.or_set_q.argtypes = [ctypes.c_int]
         L.or_hermite.restype = ctypes.c_double
         L.or_hermite.argtypes = [ctypes.c_int, ctypes.c_double]
         L.or_quadrature.argtypes = [_dp, _dp]
@@ -75,44 +77,62 @@ def _arr(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _use_q(q):
+    if lib().or_set_q(int(q)):
+        raise ValueError(f"quadrature order {q} (3 or 4)")
+    return int(q)
+
+
+def _q_of(npop):
+    q = {9: 3, 16: 4}.get(int(npop))
+    if q is None:
+        raise ValueError(f"{npop} populations: expected 9 (Q = 3) or 16 (Q = 4)")
+    return _use_q(q)
+
+
 def hermite(n: int, x: float) -> float:
     return lib().or_hermite(n, x)
 
 
-def quadrature():
-    """Ascending nodes v[4] and 1-D weights w[4] of the Q=4 Gauss-Hermite rule."""
+def quadrature(q=4):
+    """Ascending nodes v[Q] and 1-D weights w[Q] of the Gauss-Hermite rule."""
+    _use_q(q)
     v = np.zeros(4)
     w = np.zeros(4)
     lib().or_quadrature(_p(v), _p(w))
-    return v, w
+    return v[:q].copy(), w[:q].copy()
 
 
-def kernels():
-    """K^H and K~^H (4x4, row k, column k')."""
+def kernels(q=4):
+    """K^H and K~^H (QxQ, row k, column k')."""
+    _use_q(q)
     K = np.zeros(16)
     Kt = np.zeros(16)
     lib().or_kernels(_p(K), _p(Kt))
-    return K.reshape(4, 4), Kt.reshape(4, 4)
+    return K[:q * q].reshape(q, q), Kt[:q * q].reshape(q, q)
 
 
-def feq(rho, ut, up, T=1.0):
+def feq(rho, ut, up, T=1.0, q=4):
+    _use_q(q)
     out = np.zeros(16)
     lib().or_feq_thermal(rho, ut, up, T, _p(out))
-    return out
+    return out[:q * q].copy()
 
 
 def collision(f16, tau):
     f16 = _arr(f16)
+    q = _q_of(f16.size)
     out = np.zeros(16)
-    lib().or_collision(_p(f16), tau, _p(out))
-    return out
+    lib().or_collision(_p(np.concatenate([f16, np.zeros(16 - f16.size)])), tau, _p(out))
+    return out[:q * q].copy()
 
 
 def force(f16, theta, R=1.0):
     f16 = _arr(f16)
+    q = _q_of(f16.size)
     out = np.zeros(16)
-    lib().or_force(_p(f16), theta, R, _p(out))
-    return out
+    lib().or_force(_p(np.concatenate([f16, np.zeros(16 - f16.size)])), theta, R, _p(out))
+    return out[:q * q].copy()
 
 
 def weno5(h6, f6, direction, eps=1e-6):
@@ -135,10 +155,11 @@ def flux(scheme, h6, f6, direction, eps=1e-6):
 def rhs(f, R=1.0, tau=1e-3, eps=1e-6, threads=1, pole_fluxes=False, scheme="weno5",
         komissarov=False):
     f = _arr(f)
-    _, nt, np_ = f.shape
+    npop, nt, np_ = f.shape
+    _q_of(npop)
     L = np.zeros_like(f)
-    fn = np.zeros((16, np_)) if pole_fluxes else None
-    fs = np.zeros((16, np_)) if pole_fluxes else None
+    fn = np.zeros((npop, np_)) if pole_fluxes else None
+    fs = np.zeros((npop, np_)) if pole_fluxes else None
     rc = lib().or_rhs_s(nt, np_, R, tau, eps, SCHEMES[scheme], int(komissarov), _p(f), _p(L),
                         _p(fn), _p(fs), threads)
     if rc:
@@ -152,7 +173,8 @@ def step(f, nsteps, R=1.0, tau=1e-3, dt=1e-3, eps=1e-6, threads=1, budget=False,
     pole-flux mass budget when ``budget``).  ``scheme``: weno5, u1, u2, u3;
     ``komissarov``: the theta derivative of eq. (Komissarov_scheme)."""
     f = _arr(f).copy()
-    _, nt, np_ = f.shape
+    npop, nt, np_ = f.shape
+    _q_of(npop)
     b = np.zeros(1)
     rc = lib().or_step_s(nt, np_, R, tau, dt, eps, SCHEMES[scheme], int(komissarov), _p(f),
                          int(nsteps), threads, _p(b) if budget else None)
@@ -161,11 +183,12 @@ def step(f, nsteps, R=1.0, tau=1e-3, dt=1e-3, eps=1e-6, threads=1, budget=False,
     return (f, float(b[0])) if budget else f
 
 
-def init(rho, ut, up, T=None):
+def init(rho, ut, up, T=None, q=4):
+    _use_q(q)
     rho, ut, up = _arr(rho), _arr(ut), _arr(up)
     nt, np_ = rho.shape
     Ta = _arr(T) if T is not None else None
-    f = np.zeros((16, nt, np_))
+    f = np.zeros((q * q, nt, np_))
     if lib().or_init(nt, np_, _p(rho), _p(ut), _p(up), _p(Ta), _p(f)):
         raise ValueError("oracle rejected the grid")
     return f
@@ -173,7 +196,8 @@ def init(rho, ut, up, T=None):
 
 def moments(f):
     f = _arr(f)
-    _, nt, np_ = f.shape
+    npop, nt, np_ = f.shape
+    _q_of(npop)
     rho = np.zeros((nt, np_))
     ut = np.zeros_like(rho)
     up = np.zeros_like(rho)
@@ -192,7 +216,8 @@ def vorticity(ut, up, R=1.0):
 
 def diagnostics(f, R=1.0):
     f = _arr(f)
-    _, nt, np_ = f.shape
+    npop, nt, np_ = f.shape
+    _q_of(npop)
     out = np.zeros(8)
     lib().or_diagnostics(nt, np_, R, _p(f), _p(out))
     return out

@@ -9,8 +9,10 @@
  * written from the paper alone, in the paper's order and notation:
  *
  *   Sec. III.A  velocity set: Gauss-Hermite nodes (roots of H_Q) and weights,
- *               eq. (GH_weights); D2Q16 product rule, App. A.2 Table IV.
- *   Sec. III.B  BGK collision; truncated equilibrium, eq. (feq_Q=4).
+ *               eq. (GH_weights); product rules D2Q9 (Q = 3, App. A.1) and
+ *               D2Q16 (Q = 4, App. A.2 Table IV).
+ *   Sec. III.B  BGK collision; truncated equilibrium, eqs. (feq_Q=3),
+ *               (feq_Q=4).
  *   Sec. III.C  velocity derivatives by the kernels K^H, K~^H, eqs. (df),
  *               (kernels).
  *   Sec. III.D  cell-centred grid, eq. (discrete_coord_sphere).
@@ -39,25 +41,30 @@
  *     only enters the initial populations through the order-3 Hermite
  *     projection of a Maxwellian at temperature T.
  *
- * Indexing: populations k = 4*kt + kp, kt (theta component) and kp (phi
- * component) index the ascending nodes v_0 < v_1 < v_2 < v_3.  Fields are
- * [16][n_theta][n_phi] (phi fastest), 0-based s with theta_s = (s+1/2)pi/Nt
- * and phi_q = (q+1/2)2pi/Np.  Built with -ffp-contract=off: no fused
- * multiply-adds, so every product and sum is rounded as written.
+ * Indexing: populations k = Q*kt + kp, kt (theta component) and kp (phi
+ * component) index the ascending nodes v_0 < ... < v_{Q-1}.  Fields are
+ * [Q^2][n_theta][n_phi] (phi fastest), 0-based s with theta_s = (s+1/2)pi/Nt
+ * and phi_q = (q+1/2)2pi/Np.  The quadrature order Q (3 or 4, default 4) is
+ * a process-wide model choice made with or_set_q.  Built with
+ * -ffp-contract=off: no fused multiply-adds, so every product and sum is
+ * rounded as written.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #include <stdint.h>
 
-#define NV 4            /* Q, nodes per axis */
-#define NK 16           /* Q*Q populations */
+#define NVMAX 4         /* largest Q, nodes per axis */
+#define NKMAX 16        /* largest Q*Q, populations */
 #define NG 3            /* ghost layers: the WENO-5 stencil reaches 3 cells */
 
 /* advection schemes (Sec. III.E) */
 enum { OR_WENO5 = 0, OR_U1 = 1, OR_U2 = 2, OR_U3 = 3 };
 
-int or_version(void) { return 1; }
+int or_version(void) { return 2; }
+
+/* The quadrature order Q of the model (3: D2Q9, 4: D2Q16). */
+static int NV = 4, NK = 16;
 
 /* ---------------------------------------------------------------------- */
 /* Sec. III.A: probabilists' Hermite polynomials, eq. (hermite_polynomials)
@@ -82,14 +89,18 @@ static double factorial(int n)
     return r;
 }
 
-/* Nodes: roots of H_4(x) = x^4 - 6x^2 + 3 (App. A.2, Fig. stencils), i.e.
- * x^2 = 3 -/+ sqrt(6), sorted ascending.  Weights eq. (GH_weights):
- * w_k = Q! / H_{Q+1}(v_k)^2.                                              */
-void or_quadrature(double v[NV], double w[NV])
+/* Nodes: roots of H_Q (Fig. stencils), ascending.  Q = 4: H_4(x) = x^4 -
+ * 6x^2 + 3, x^2 = 3 -/+ sqrt(6) (App. A.2); Q = 3: H_3(x) = x^3 - 3x, x = 0,
+ * +-sqrt(3) (App. A.1).  Weights eq. (GH_weights): w_k = Q! / H_{Q+1}(v_k)^2. */
+void or_quadrature(double v[NVMAX], double w[NVMAX])
 {
-    double a = sqrt(3.0 + sqrt(6.0));
-    double b = sqrt(3.0 - sqrt(6.0));
-    v[0] = -a; v[1] = -b; v[2] = b; v[3] = a;
+    if (NV == 4) {
+        double a = sqrt(3.0 + sqrt(6.0));
+        double b = sqrt(3.0 - sqrt(6.0));
+        v[0] = -a; v[1] = -b; v[2] = b; v[3] = a;
+    } else {
+        v[0] = -sqrt(3.0); v[1] = 0.0; v[2] = sqrt(3.0);
+    }
     for (int k = 0; k < NV; ++k) {
         double h = or_hermite(NV + 1, v[k]);
         w[k] = factorial(NV) / (h * h);
@@ -100,9 +111,9 @@ void or_quadrature(double v[NV], double w[NV])
  *   K_{k,k'}  = -w_k sum_{l=0}^{Q-1} H_{l+1}(v_k) H_l(v_k') / l!
  *   Kt_{k,k'} = -w_k sum_{l=0}^{Q-1} H_{l+1}(v_k) [H_{l+1}(v_k') + l H_{l-1}(v_k')] / l!
  * Row-major K[k*4 + k'].                                                  */
-void or_kernels(double K[NV * NV], double Kt[NV * NV])
+void or_kernels(double K[NKMAX], double Kt[NKMAX])
 {
-    double v[NV], w[NV];
+    double v[NVMAX], w[NVMAX];
     or_quadrature(v, w);
     for (int k = 0; k < NV; ++k)
         for (int kp = 0; kp < NV; ++kp) {
@@ -117,8 +128,9 @@ void or_kernels(double K[NV * NV], double Kt[NV * NV])
         }
 }
 
-/* Process-wide constant tables, built once from the definitions above. */
-static double g_v[NV], g_w1[NV], g_K[NV * NV], g_Kt[NV * NV];
+/* Process-wide constant tables, built from the definitions above for the
+ * current Q. */
+static double g_v[NVMAX], g_w1[NVMAX], g_K[NKMAX], g_Kt[NKMAX];
 static int g_ready = 0;
 
 static void tables(void)
@@ -129,14 +141,27 @@ static void tables(void)
     g_ready = 1;
 }
 
+int or_set_q(int q)
+{
+    if (q != 3 && q != 4) return -1;
+    NV = q;
+    NK = q * q;
+    g_ready = 0;
+    tables();
+    return 0;
+}
+
+int or_get_q(void) { return NV; }
+
 /* ---------------------------------------------------------------------- */
 /* Sec. III.B, eq. (feq_Q=4): isothermal equilibrium (T0 = 1)
  *   f^eq_k = n w_k [1 + v.u + ((v.u)^2 - u^2)/2 + v.u((v.u)^2 - 3u^2)/6]
+ * and for Q = 3 eq. (feq_Q=3), the same without the cubic term.
  * With T != 1 the order-2 and order-3 Hermite coefficients gain the thermal
  * parts n(T-1)delta and n(T-1)(u delta)_sym, which add
  *   (T-1)(|v|^2 - 2)/2  and  v.u (T-1)(|v|^2 - 4)/2
- * inside the bracket (used for initial states only).                      */
-void or_feq_thermal(double n, double ut, double up, double T, double feq[NK])
+ * inside the bracket (used for initial states only; Q = 3 keeps the first).  */
+void or_feq_thermal(double n, double ut, double up, double T, double feq[NKMAX])
 {
     tables();
     double u2 = ut * ut + up * up;
@@ -146,15 +171,14 @@ void or_feq_thermal(double n, double ut, double up, double T, double feq[NK])
             double vt = g_v[kt], vp = g_v[kp];
             double vu = vt * ut + vp * up;
             double v2 = vt * vt + vp * vp;
-            double br = 1.0 + vu
-                      + 0.5 * (vu * vu - u2 + dT * (v2 - 2.0))
-                      + vu * (vu * vu - 3.0 * u2 + 3.0 * dT * (v2 - 4.0)) / 6.0;
+            double br = 1.0 + vu + 0.5 * (vu * vu - u2 + dT * (v2 - 2.0));
+            if (NV == 4) br += vu * (vu * vu - 3.0 * u2 + 3.0 * dT * (v2 - 4.0)) / 6.0;
             feq[kt * NV + kp] = n * g_w1[kt] * g_w1[kp] * br;
         }
 }
 
 /* Eq. (f_moments_sum): n = sum f, n u = sum f v. */
-static void moments(const double f[NK], double* n, double* ut, double* up)
+static void moments(const double f[NKMAX], double* n, double* ut, double* up)
 {
     double s0 = 0.0, st = 0.0, sp = 0.0;
     for (int kt = 0; kt < NV; ++kt)
@@ -170,10 +194,10 @@ static void moments(const double f[NK], double* n, double* ut, double* up)
 }
 
 /* BGK, Sec. III.B: C_k = -(f_k - f^eq_k)/tau, f^eq at the local n, u, T0 = 1. */
-void or_collision(const double f[NK], double tau, double C[NK])
+void or_collision(const double f[NKMAX], double tau, double C[NKMAX])
 {
     tables();
-    double n, ut, up, feq[NK];
+    double n, ut, up, feq[NKMAX];
     moments(f, &n, &ut, &up);
     or_feq_thermal(n, ut, up, 1.0, feq);
     for (int k = 0; k < NK; ++k) C[k] = -(f[k] - feq[k]) / tau;
@@ -183,7 +207,7 @@ void or_collision(const double f[NK], double tau, double C[NK])
  *   G_k = -(cos th/(R sin th)) [ v_{kp}^2 (df/dv_th)_k - v_{kt} (d(f v_ph)/dv_ph)_k ]
  * with (df/dv_th)_{kt,kp} = sum_{b} K_{kt,b} f_{b,kp} and
  *      (d(f v_ph)/dv_ph)_{kt,kp} = sum_{b} Kt_{kp,b} f_{kt,b}   (eqs. (df)). */
-void or_force(const double f[NK], double theta, double R, double G[NK])
+void or_force(const double f[NKMAX], double theta, double R, double G[NKMAX])
 {
     tables();
     double cotr = cos(theta) / (R * sin(theta));
@@ -371,7 +395,7 @@ static int rhs_ext(int nt, int np, double R, double tau, double eps, int scheme,
         double th = (s + 0.5) * dth;
         double rs = R * sin(th);
         double rk = R * (cos(s * dth) - cos((s + 1) * dth));   /* Komissarov band */
-        double fc[NK], C[NK], G[NK];
+        double fc[NKMAX], C[NKMAX], G[NKMAX];
         for (int q = 0; q < np; ++q) {
             for (int k = 0; k < NK; ++k) fc[k] = *E(&x, k, s, q);
             or_collision(fc, tau, C);
@@ -481,7 +505,7 @@ int or_init(int nt, int np, const double* rho, const double* ut, const double* u
             const double* T, double* f)
 {
     if (check_grid(nt, np)) return -1;
-    double feq[NK];
+    double feq[NKMAX];
     for (int s = 0; s < nt; ++s)
         for (int q = 0; q < np; ++q) {
             size_t c = (size_t)s * np + q;
@@ -497,7 +521,7 @@ int or_moments(int nt, int np, const double* f, double* rho, double* ut,
 {
     if (check_grid(nt, np)) return -1;
     tables();
-    double fc[NK];
+    double fc[NKMAX];
     for (int s = 0; s < nt; ++s)
         for (int q = 0; q < np; ++q) {
             size_t c = (size_t)s * np + q;
@@ -569,7 +593,7 @@ int or_diagnostics(int nt, int np, double R, const double* f, double out[8])
         double st = sin((s + 0.5) * dth);
         double dA = R * R * st * dth * dph;
         for (int q = 0; q < np; ++q) {
-            double fc[NK], e = 0.0;
+            double fc[NKMAX], e = 0.0;
             for (int k = 0; k < NK; ++k) {
                 fc[k] = f[((size_t)k * nt + s) * np + q];
                 if (!isfinite(fc[k])) nbad += 1.0;
