@@ -189,7 +189,8 @@ def cpu_baseline(state, threads):
 def run_schemes(state, steps):
     """Cost of the advection schemes on the benchmark grid: MLUPS of U1, U2, U3
     and WENO-5, each in the standard and the Komissarov form, FP32 and FP64
-    deviation store, `steps` timed steps after 2 warm-up steps."""
+    deviation store, and of the D2Q9 model (Q = 3) with WENO-5; `steps` timed
+    steps after 2 warm-up steps."""
     import torch
     from paper_2504_15574_amd import Solver
     out = {}
@@ -211,6 +212,22 @@ def run_schemes(state, steps):
                 sol.close()
                 out[f"{storage}/{scheme}{'+komissarov' if kom else ''}"] = {
                     "mlups": round(N_THETA * N_PHI / (ms * 1e-3) / 1e6, 1), "finite": bool(ok)}
+    for storage in ("f32", "f64"):
+        sol = Solver(N_THETA, N_PHI, TAU, storage=storage, q=3)
+        sol.init_fields(*state)
+        sol.step(2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sol.stream)
+        sol.step(steps)
+        e1.record(sol.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ok = sol.diagnostics(raise_unstable=False)[4] == 0
+        sol.close()
+        out[f"{storage}/d2q9-weno5"] = {"mlups": round(N_THETA * N_PHI / (ms * 1e-3) / 1e6, 1),
+                                        "finite": bool(ok)}
     return out
 
 

@@ -12,9 +12,11 @@
  *    (s + 1/2) pi / n_theta, phi_q = (q + 1/2) 2 pi / n_phi.
  *  - Fields are FP64, row-major [n_theta][n_phi] (phi fastest).  Velocities are
  *    the orthonormal (vielbein) components u^theta, u^phi.
- *  - Populations exchanged through the ABI are FP64 [16][n_theta][n_phi] with
- *    k = 4*k_theta + k_phi over the ascending nodes -sqrt(3+sqrt6),
- *    -sqrt(3-sqrt6), +sqrt(3-sqrt6), +sqrt(3+sqrt6) (App. A.2).
+ *  - Populations exchanged through the ABI are FP64 [Q*Q][n_theta][n_phi] with
+ *    k = Q*k_theta + k_phi over the ascending nodes: Q = 4 (D2Q16, App. A.2)
+ *    -sqrt(3+sqrt6), -sqrt(3-sqrt6), +sqrt(3-sqrt6), +sqrt(3+sqrt6); Q = 3
+ *    (D2Q9, App. A.1) -sqrt3, 0, +sqrt3.  The equilibrium is eq. (feq_Q=4)
+ *    or eq. (feq_Q=3).
  *  - "ptr_on_device" = 1: the pointer is HIP device memory and the call is
  *    asynchronous on the context stream; 0: host memory and the call
  *    synchronises the context stream before returning.
@@ -74,7 +76,7 @@ typedef struct {
     uint32_t abi_version;  /* must equal VLBM_ABI_VERSION                            */
     int32_t n_theta;       /* >= 3 (pole ghosts mirror rows 0..2)                    */
     int32_t n_phi;         /* 1 (axisymmetric) or even (phi + pi must be a column)   */
-    int32_t q;             /* Gauss-Hermite points per axis; only 4 is implemented   */
+    int32_t q;             /* Gauss-Hermite points per axis: 4 (D2Q16) or 3 (D2Q9)   */
     double radius;         /* R > 0                                                  */
     double tau;            /* BGK relaxation time > 0 (nu = tau at T0 = 1)           */
     double dt;             /* time step > 0; not clamped (see vlbm_suggest_dt)       */
@@ -133,10 +135,10 @@ vlbm_status vlbm_diagnostics(vlbm_ctx* ctx, double out[8]);
  * velocity inversion at phi + pi.  Output field as above. */
 vlbm_status vlbm_vorticity(vlbm_ctx* ctx, double* omega, int ptr_on_device);
 
-/* Decode the current populations f_n to FP64 [16][n_theta][n_phi]. */
+/* Decode the current populations f_n to FP64 [Q*Q][n_theta][n_phi]. */
 vlbm_status vlbm_get_populations(vlbm_ctx* ctx, double* f, int ptr_on_device);
 
-/* Encode FP64 populations [16][n_theta][n_phi] into f_n (checkpoint resume). */
+/* Encode FP64 populations [Q*Q][n_theta][n_phi] into f_n (checkpoint resume). */
 vlbm_status vlbm_set_populations(vlbm_ctx* ctx, const double* f, int ptr_on_device);
 
 /* Moment correction (used by the learned closure): in every cell, with rho, u

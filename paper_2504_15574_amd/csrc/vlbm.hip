@@ -28,8 +28,8 @@
 
 namespace {
 
-constexpr int NQ = 4;    // nodes per axis
-constexpr int NK = 16;   // populations
+constexpr int NQMAX = 4;    // nodes per axis (Q = 3: D2Q9, Q = 4: D2Q16)
+constexpr int NKMAX = 16;   // populations Q * Q
 constexpr int NGH = 3;   // ghost layers of the 6-point WENO-5 stencil
 
 // ---------------------------------------------------------------------------
@@ -53,17 +53,19 @@ vlbm_status fail(vlbm_status st, const char* fmt, ...) {
 
 // ---------------------------------------------------------------------------
 // constant tables passed by value to every kernel
+// (arrays packed with the stride Q of the model: k = Q kt + kp)
 struct Consts {
-    double v[NQ];         // ascending Gauss-Hermite nodes (roots of H_4)
-    double wk[NK];        // product weights w_k
-    double K[NQ * NQ];    // K^H,  row k, column k'
-    double Kt[NQ * NQ];   // K~^H
-    double scale[NK];     // FP16 storage scale 2^e_k (1 for the other formats)
-    double iscale[NK];    // 1 / scale
+    int q;                    // quadrature order Q (3 or 4)
+    double v[NQMAX];          // ascending Gauss-Hermite nodes (roots of H_Q)
+    double wk[NKMAX];         // product weights w_k
+    double K[NKMAX];          // K^H,  row k, column k'
+    double Kt[NKMAX];         // K~^H
+    double scale[NKMAX];      // FP16 storage scale 2^e_k (1 for the other formats)
+    double iscale[NKMAX];     // 1 / scale
     // rank-1 form of the inertial force: population (kt, kp) adds
     //   fa[kp][a][kt] * cot g  to G_(a, kp)   and   fb[kt][b][kp] * cot g  to G_(kt, b)
-    double fa[NQ * NQ * NQ];   // -v_kp^2 K[a][kt]
-    double fb[NQ * NQ * NQ];   //  v_kt Kt[b][kp]
+    double fa[NQMAX * NKMAX];   // -v_kp^2 K[a][kt]
+    double fb[NQMAX * NKMAX];   //  v_kt Kt[b][kp]
 };
 
 // per-row tables in the workspace (FP64)
@@ -80,7 +82,7 @@ struct Rows {
 // the constants the stage kernel uses, in its arithmetic type
 template <class T>
 struct ConstsT {
-    T v[NQ], wk[NK], vw[NK], fa[NQ * NQ * NQ], fb[NQ * NQ * NQ], scale[NK], iscale[NK];
+    T v[NQMAX], wk[NKMAX], vw[NKMAX], fa[NQMAX * NKMAX], fb[NQMAX * NKMAX], scale[NKMAX], iscale[NKMAX];
 };
 
 // One run (context) at one RK stage, in device memory inside the context's
@@ -288,8 +290,9 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
 // GEN: the general variant (any advection scheme, Komissarov interface factor),
 // launched when a run of the launch needs it; the default WENO-5 standard form
 // uses the specialised variant, which keeps two registers fewer.
-template <class St, bool BATCH, class Tl, bool GEN>
+template <class St, bool BATCH, class Tl, bool GEN, int NQ>
 __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
+    constexpr int NK = NQ * NQ;
     constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, LC = Tl::LC, LT = Tl::LT;
     constexpr int NLOAD = Tl::NLOAD, NFT = Tl::NFT, NFP = Tl::NFP;
     using T = typename St::T;
@@ -369,7 +372,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         return St::bld(rin, (((uint32_t)k * planeB) ^ lm[j]) + la[j], 0, (float)C.iscale[k]);
     };
     auto lstore = [&](int k, int buf, T v0, T v1) {
-        const T vt = C.v[k >> 2];
+        const T vt = C.v[k / NQ];
         tile[buf][ldst[0]] = v0;
         tile[buf][ldst[1]] = v1;
         tileh[buf][ldst[0]] = (vt * lsin[0]) * v0;
@@ -427,7 +430,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-        const int kt = k >> 2, kp = k & 3;
+        const int kt = k / NQ, kp = k % NQ;
         const int tb = k % 3, fb = k & 1;
         T gself, Ftself, Flself = T(0);
         // global loads of population k+2 (written to LDS after the barrier)
@@ -450,14 +453,14 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             gself = g[3];                                // this thread's cell (row ti, column tc)
             T F;
             if (scheme == VLBM_ADV_WENO5) {
-                if (kt >= 2)
+                if (2 * kt >= NQ)                        // v_kt > 0 (zero for the middle Q = 3 node)
                     F = weno5(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4], eps12,
                               vw * dCp1, vw * dCp3);
                 else
                     F = weno5(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1], eps12,
                               vw * dCm1, vw * dCm3);
             } else {
-                F = kt >= 2 ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
+                F = 2 * kt >= NQ ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
             }
             if constexpr (GEN) F *= sIf;
             fth[fb][tid] = F;
@@ -470,12 +473,12 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             for (int m = 0; m < 6; ++m) g[m] = tile[tb][pbase + m];
             T F;
             if (scheme == VLBM_ADV_WENO5) {
-                if (kp >= 2)
+                if (2 * kp >= NQ)
                     F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
                 else
                     F = weno5(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1], eps12, T(0), T(0));
             } else {
-                F = kp >= 2 ? upwind(scheme, g[1], g[2], g[3]) : upwind(scheme, g[4], g[3], g[2]);
+                F = 2 * kp >= NQ ? upwind(scheme, g[1], g[2], g[3]) : upwind(scheme, g[4], g[3], g[2]);
             }
             Flself = C.v[kp] * F;                        // left face of this thread's cell
             fph[fb][pslot] = Flself;
@@ -503,10 +506,15 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         if (k + 2 < NK) lstore(k + 2, (k + 2) % 3, nx0, nx1);
         // keep this population's register arithmetic in place: deferring it past
         // the following barriers would keep every population's inputs live at once
-        asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
-                     "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]), "+v"(acc[9]),
-                     "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]), "+v"(acc[14]),
-                     "+v"(acc[15]), "+v"(drho), "+v"(jt), "+v"(jp));
+        if constexpr (NK == 16)
+            asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
+                         "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]), "+v"(acc[9]),
+                         "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]), "+v"(acc[14]),
+                         "+v"(acc[15]), "+v"(drho), "+v"(jt), "+v"(jp));
+        else
+            asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
+                         "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]), "+v"(drho),
+                         "+v"(jt), "+v"(jp));
     }
 
     if (!valid) return;
@@ -525,9 +533,11 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-            const T vt = C.v[k >> 2], vp = C.v[k & 3];
+            const T vt = C.v[k / NQ], vp = C.v[k % NQ];
             const T xi = vt * ut + vp * up;
-            const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
+            // eq. (feq_Q=4); Q = 3 drops the cubic term, eq. (feq_Q=3)
+            T pm1 = xi + T(0.5) * (xi * xi - u2);
+            if constexpr (NQ == 4) pm1 += xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
             const T y = acc[k] + dti * C.wk[k] * (drho + rho * pm1);
             T o = cb * y;
             if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
@@ -559,9 +569,11 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const T g = gk[k];
-            const T vt = C.v[k >> 2], vp = C.v[k & 3];
+            const T vt = C.v[k / NQ], vp = C.v[k % NQ];
             const T xi = vt * ut + vp * up;
-            const T pm1 = xi + T(0.5) * (xi * xi - u2) + xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
+            // eq. (feq_Q=4); Q = 3 drops the cubic term, eq. (feq_Q=3)
+            T pm1 = xi + T(0.5) * (xi * xi - u2);
+            if constexpr (NQ == 4) pm1 += xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
             const T inc = acc[k] + dti * (C.wk[k] * (drho + rho * pm1) - g);
             // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]
             T d = cb * inc;
@@ -574,7 +586,8 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 
 // ---------------------------------------------------------------------------
 // Equilibrium initialisation: g_k = f^eq_k(rho, u, T) - w_k rho0 with the
-// thermal order-2/3 Hermite terms for T != 1, computed in FP64.
+// thermal order-2/3 Hermite terms for T != 1 (order 2 only for Q = 3),
+// computed in FP64.
 template <class St>
 __global__ void init_kernel(const double* rho, const double* ut, const double* up,
                             const double* Tf, void* outv, Consts c, int n, double rho0) {
@@ -584,12 +597,12 @@ __global__ void init_kernel(const double* rho, const double* ut, const double* u
     const double r = rho[i], a = ut[i], b = up[i];
     const double dT = Tf ? Tf[i] - 1.0 : 0.0;
     const double u2 = a * a + b * b;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        const double vt = c.v[k >> 2], vp = c.v[k & 3];
+    const int q = c.q;
+    for (int k = 0; k < q * q; ++k) {
+        const double vt = c.v[k / q], vp = c.v[k % q];
         const double xi = vt * a + vp * b, v2 = vt * vt + vp * vp;
-        const double pm1 = xi + 0.5 * (xi * xi - u2 + dT * (v2 - 2.0)) +
-                           xi * (xi * xi - 3.0 * u2 + 3.0 * dT * (v2 - 4.0)) / 6.0;
+        double pm1 = xi + 0.5 * (xi * xi - u2 + dT * (v2 - 2.0));
+        if (q == 4) pm1 += xi * (xi * xi - 3.0 * u2 + 3.0 * dT * (v2 - 4.0)) / 6.0;
         const double g = c.wk[k] * ((r - rho0) + r * pm1);
         St::st(out, (size_t)k * n + i, (typename St::T)g, c.scale[k]);
     }
@@ -626,8 +639,8 @@ __device__ __forceinline__ void cell_moments(const typename St::S* in, size_t i,
                                              int& nbad);
 
 // Moment correction: f_k += f^eq_k(rho + d_rho, u + d_u) - f^eq_k(rho, u) with
-// the isothermal order-3 equilibrium (eq. (feq_Q=4)); the non-equilibrium part
-// of f is kept.
+// the isothermal equilibrium (eqs. (feq_Q=3), (feq_Q=4)); the non-equilibrium
+// part of f is kept.
 template <class St>
 __global__ void correct_kernel(void* io, const double* drho, const double* dut, const double* dup,
                                Consts c, int n, double rho0) {
@@ -639,12 +652,15 @@ __global__ void correct_kernel(void* io, const double* drho, const double* dut, 
     cell_moments<St>(f, i, n, c, rho0, r, a, b, t, e, nb);
     const double r2 = r + drho[i], a2 = a + dut[i], b2 = b + dup[i];
     const double u2 = a * a + b * b, w2 = a2 * a2 + b2 * b2;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        const double vt = c.v[k >> 2], vp = c.v[k & 3];
+    const int q = c.q;
+    for (int k = 0; k < q * q; ++k) {
+        const double vt = c.v[k / q], vp = c.v[k % q];
         const double x1 = vt * a + vp * b, x2 = vt * a2 + vp * b2;
-        const double p1 = x1 + 0.5 * (x1 * x1 - u2) + x1 * (x1 * x1 - 3.0 * u2) / 6.0;
-        const double p2 = x2 + 0.5 * (x2 * x2 - w2) + x2 * (x2 * x2 - 3.0 * w2) / 6.0;
+        double p1 = x1 + 0.5 * (x1 * x1 - u2), p2 = x2 + 0.5 * (x2 * x2 - w2);
+        if (q == 4) {
+            p1 += x1 * (x1 * x1 - 3.0 * u2) / 6.0;
+            p2 += x2 * (x2 * x2 - 3.0 * w2) / 6.0;
+        }
         const size_t o = (size_t)k * n + i;
         const double g = (double)St::ld(f, o, c.iscale[k]) + c.wk[k] * ((r2 - r) + r2 * p2 - r * p1);
         St::st(f, o, (typename St::T)g, c.scale[k]);
@@ -656,27 +672,27 @@ __device__ __forceinline__ void cell_moments(const typename St::S* in, size_t i,
                                              const Consts& c, double rho0, double& rho,
                                              double& ut, double& up, double& T, double& e,
                                              int& nbad) {
-    double g[NK];
+    double g[NKMAX];
     double dr = 0, jt = 0, jp = 0;
     nbad = 0;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
+    const int q = c.q;
+    for (int k = 0; k < q * q; ++k) {
         g[k] = (double)St::ld(in, (size_t)k * n + i, c.iscale[k]);
         nbad += isfinite(g[k]) ? 0 : 1;
         dr += g[k];
-        jt += c.v[k >> 2] * g[k];
-        jp += c.v[k & 3] * g[k];
+        jt += c.v[k / q] * g[k];
+        jp += c.v[k % q] * g[k];
     }
     rho = rho0 + dr;
     ut = jt / rho;
     up = jp / rho;
     double th = 0, en = 0;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
+    for (int k = 0; k < q * q; ++k) {
         const double f = c.wk[k] * rho0 + g[k];
-        const double dt_ = c.v[k >> 2] - ut, dp_ = c.v[k & 3] - up;
+        const double vt = c.v[k / q], vp = c.v[k % q];
+        const double dt_ = vt - ut, dp_ = vp - up;
         th += f * (dt_ * dt_ + dp_ * dp_);
-        en += 0.5 * f * (c.v[k >> 2] * c.v[k >> 2] + c.v[k & 3] * c.v[k & 3]);
+        en += 0.5 * f * (vt * vt + vp * vp);
     }
     T = th / (2.0 * rho);
     e = en;
@@ -835,40 +851,51 @@ struct Rule {
     float vo, vi, woo, woi, wii;
     double e00, e20;
 };
-Rule search() {
+// n_out, n_in: outer and inner nodes per axis (Q = 4: 2 and 2; Q = 3: the
+// nodes +-sqrt3 and the node 0, which stays exactly 0).  A population with m
+// inner components has class weight w_{oo}, w_{oi}, w_{ii} for m = 0, 1, 2.
+Rule search(int q) {
     const double r6 = std::sqrt(6.0);
-    const double vo = std::sqrt(3.0 + r6), vi = std::sqrt(3.0 - r6);
-    const double h5o = vo * vo * vo * vo * vo - 10 * vo * vo * vo + 15 * vo;
-    const double h5i = vi * vi * vi * vi * vi - 10 * vi * vi * vi + 15 * vi;
-    const double wo = 24.0 / (h5o * h5o), wi = 24.0 / (h5i * h5i);
+    const double vo = q == 4 ? std::sqrt(3.0 + r6) : std::sqrt(3.0);
+    const double vi = q == 4 ? std::sqrt(3.0 - r6) : 0.0;
+    const int n_out = 2, n_in = q - 2;
+    auto w1 = [&](double v) {
+        const double h = q == 4 ? v * v * v * v * v - 10 * v * v * v + 15 * v : v * v * v * v - 6 * v * v + 3;
+        return (q == 4 ? 24.0 : 6.0) / (h * h);
+    };
+    const double wo = w1(vo), wi = w1(vi);
     const i128 one = (i128)1 << FXS, lim00 = (i128)(2e-9 * std::ldexp(1.0, FXS));
     constexpr int KU = 10;
+    const int KI = q == 4 ? KU : 0;        // the zero node is exact
     Rule best{};
     i128 best20 = -1;
     int bestmove = 0;
     for (int a = -KU; a <= KU; ++a) {
         const float fvo = step_ulps((float)vo, a);
-        for (int b = -KU; b <= KU; ++b) {
+        for (int b = -KI; b <= KI; ++b) {
             const float fvi = step_ulps((float)vi, b);
             for (int c = -KU; c <= KU; ++c) {
                 const float woo = step_ulps((float)(wo * wo), c);
                 for (int d = -KU; d <= KU; ++d) {
                     const float woi = step_ulps((float)(wo * wi), d);
-                    const float c0 = (float)((1.0 - 4.0 * (double)woo - 8.0 * (double)woi) / 4.0);
+                    const float c0 = (float)((1.0 - n_out * n_out * (double)woo -
+                                              2.0 * n_out * n_in * (double)woi) / (n_in * n_in));
                     for (int e = -1; e <= 1; ++e) {
                         const float wii = step_ulps(c0, e);
-                        const i128 e00 = 4 * exact(woo) + 8 * exact(woi) + 4 * exact(wii) - one;
+                        const i128 e00 = n_out * n_out * exact(woo) + 2 * n_out * n_in * exact(woi) +
+                                         n_in * n_in * exact(wii) - one;
                         if (e00 > lim00 || -e00 > lim00) continue;
-                        i128 e20 = 4 * (exact(woo, fvo, fvo) + exact(woi, fvo, fvo) +
-                                        exact(woi, fvi, fvi) + exact(wii, fvi, fvi)) - one;
+                        // sum_k w_k v_theta^2 = n_out v_o^2 (n_out w_oo + n_in w_oi)
+                        //                     + n_in v_i^2 (n_out w_oi + n_in w_ii)
+                        const i128 s20 = n_out * (n_out * exact(woo, fvo, fvo) + n_in * exact(woi, fvo, fvo)) +
+                                         n_in * (n_out * exact(woi, fvi, fvi) + n_in * exact(wii, fvi, fvi));
+                        i128 e20 = s20 - one;
                         if (e20 < 0) e20 = -e20;
                         const int move = std::abs(a) + std::abs(b) + std::abs(c) + std::abs(d);
                         if (best20 < 0 || e20 < best20 || (e20 == best20 && move < bestmove)) {
                             best20 = e20;
                             bestmove = move;
-                            best = Rule{fvo, fvi, woo, woi, wii, to_d(e00), 0.0};
-                            best.e20 = to_d(4 * (exact(woo, fvo, fvo) + exact(woi, fvo, fvo) +
-                                                 exact(woi, fvi, fvi) + exact(wii, fvi, fvi)) - one);
+                            best = Rule{fvo, fvi, woo, woi, wii, to_d(e00), to_d(s20 - one)};
                         }
                     }
                 }
@@ -877,43 +904,67 @@ Rule search() {
     }
     return best;
 }
-const Rule& rule() {
-    static const Rule r = search();
-    return r;
+const Rule& rule(int q) {
+    static const Rule r4 = search(4);
+    static const Rule r3 = search(3);
+    return q == 3 ? r3 : r4;
+}
+// FP32 nodes and weights of the rule for a population k = q kt + kp
+inline void fp32_rule(int q, float v[NQMAX], float w[NKMAX]) {
+    const Rule& r = rule(q);
+    if (q == 4) {
+        v[0] = -r.vo; v[1] = -r.vi; v[2] = r.vi; v[3] = r.vo;
+    } else {
+        v[0] = -r.vo; v[1] = 0.0f; v[2] = r.vo;
+    }
+    auto inner = [&](int i) { return (int)(q == 4 ? (i == 1 || i == 2) : i == 1); };
+    const float cls[3] = {r.woo, r.woi, r.wii};
+    for (int k = 0; k < q * q; ++k) w[k] = cls[inner(k / q) + inner(k % q)];
 }
 }  // namespace quad32
 
-void build_consts(Consts& c, int storage) {
-    const double r6 = std::sqrt(6.0);
-    c.v[0] = -std::sqrt(3.0 + r6);
-    c.v[1] = -std::sqrt(3.0 - r6);
-    c.v[2] = std::sqrt(3.0 - r6);
-    c.v[3] = std::sqrt(3.0 + r6);
-    double w1[NQ];
-    for (int i = 0; i < NQ; ++i) {
-        const double h5 = hermite(5, c.v[i]);
-        w1[i] = 24.0 / (h5 * h5);          // Q! / H_{Q+1}(v)^2 with Q = 4
+// Nodes (roots of H_Q: Q = 4, x^2 = 3 -+ sqrt6, App. A.2; Q = 3, x = 0, +-sqrt3,
+// App. A.1), weights Q! / H_{Q+1}(v)^2, the kernels K^H, K~^H of eqs. (KH),
+// (KtildeH) and the rank-1 force coefficients, all packed with stride Q.
+void build_consts(Consts& c, int storage, int q) {
+    c = Consts{};
+    c.q = q;
+    if (q == 4) {
+        const double r6 = std::sqrt(6.0);
+        c.v[0] = -std::sqrt(3.0 + r6);
+        c.v[1] = -std::sqrt(3.0 - r6);
+        c.v[2] = std::sqrt(3.0 - r6);
+        c.v[3] = std::sqrt(3.0 + r6);
+    } else {
+        c.v[0] = -std::sqrt(3.0);
+        c.v[1] = 0.0;
+        c.v[2] = std::sqrt(3.0);
     }
-    for (int k = 0; k < NK; ++k) c.wk[k] = w1[k >> 2] * w1[k & 3];
-    const double fact[NQ] = {1.0, 1.0, 2.0, 6.0};
-    for (int i = 0; i < NQ; ++i)
-        for (int j = 0; j < NQ; ++j) {
+    const double fact[NQMAX + 1] = {1.0, 1.0, 2.0, 6.0, 24.0};
+    double w1[NQMAX];
+    for (int i = 0; i < q; ++i) {
+        const double h = hermite(q + 1, c.v[i]);
+        w1[i] = fact[q] / (h * h);
+    }
+    for (int k = 0; k < q * q; ++k) c.wk[k] = w1[k / q] * w1[k % q];
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
             double a = 0.0, b = 0.0;
-            for (int l = 0; l < NQ; ++l) {
+            for (int l = 0; l < q; ++l) {
                 const double hl1 = hermite(l + 1, c.v[i]) / fact[l];
                 a += hl1 * hermite(l, c.v[j]);
                 b += hl1 * (hermite(l + 1, c.v[j]) + l * hermite(l - 1, c.v[j]));
             }
-            c.K[i * NQ + j] = -w1[i] * a;
-            c.Kt[i * NQ + j] = -w1[i] * b;
+            c.K[i * q + j] = -w1[i] * a;
+            c.Kt[i * q + j] = -w1[i] * b;
         }
-    for (int kt = 0; kt < NQ; ++kt)
-        for (int kp = 0; kp < NQ; ++kp)
-            for (int a = 0; a < NQ; ++a) {
-                c.fa[(kp * NQ + a) * NQ + kt] = -c.v[kp] * c.v[kp] * c.K[a * NQ + kt];
-                c.fb[(kt * NQ + a) * NQ + kp] = c.v[kt] * c.Kt[a * NQ + kp];
+    for (int kt = 0; kt < q; ++kt)
+        for (int kp = 0; kp < q; ++kp)
+            for (int a = 0; a < q; ++a) {
+                c.fa[(kp * q + a) * q + kt] = -c.v[kp] * c.v[kp] * c.K[a * q + kt];
+                c.fb[(kt * q + a) * q + kp] = c.v[kt] * c.Kt[a * q + kp];
             }
-    for (int k = 0; k < NK; ++k) {
+    for (int k = 0; k < q * q; ++k) {
         double sc = 1.0;
         if (storage == VLBM_STORE_F16_DEV) sc = std::ldexp(1.0, 10 - (int)std::lround(std::log2(c.wk[k])));
         c.scale[k] = sc;
@@ -987,18 +1038,19 @@ void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
             }
             c2[dir * (nt + 1) + i] = rec * h.sI[i];
         }
-    h.rest.assign((size_t)NK * nt, 0.0);
+    const int q = c.q;
+    h.rest.assign((size_t)q * q * nt, 0.0);
     const double r0 = p.rho0;
-    for (int k = 0; k < NK; ++k) {
-        const int kt = k >> 2, kp = k & 3;
+    for (int k = 0; k < q * q; ++k) {
+        const int kt = k / q, kp = k % q;
         const int dir = c.v[kt] > 0 ? 0 : 1;
         for (int s = 0; s < nt; ++s) {
             const double vw = c.v[kt] * c.wk[k] * r0;
             const double adv = -h.inv_sdth[s] * vw * (c2[dir * (nt + 1) + s + 1] - c2[dir * (nt + 1) + s]);
             double dfdvt = 0.0, dfvdvp = 0.0;
-            for (int b = 0; b < NQ; ++b) {
-                dfdvt += c.K[kt * NQ + b] * c.wk[b * NQ + kp] * r0;
-                dfvdvp += c.Kt[kp * NQ + b] * c.wk[kt * NQ + b] * r0;
+            for (int b = 0; b < q; ++b) {
+                dfdvt += c.K[kt * q + b] * c.wk[b * q + kp] * r0;
+                dfvdvp += c.Kt[kp * q + b] * c.wk[kt * q + b] * r0;
             }
             const double G = -h.cot[s] * (c.v[kp] * c.v[kp] * dfdvt - c.v[kt] * dfvdvp);
             h.rest[(size_t)k * nt + s] = p.dt * (adv + G);
@@ -1022,14 +1074,15 @@ Layout layout_of(const vlbm_params& p) {
     Layout L{};
     const size_t n = (size_t)p.n_theta * p.n_phi;
     size_t off = 0;
-    const size_t fb = align_up(NK * n * store_bytes(p.storage));
+    const size_t nk = (size_t)p.q * p.q;
+    const size_t fb = align_up(nk * n * store_bytes(p.storage));
     for (int i = 0; i < 3; ++i) { L.fbuf[i] = off; off += fb; }
     L.sinv = off; off += align_up(sizeof(double) * (p.n_theta + 2 * NGH));
     L.inv_sdth = off; off += align_up(sizeof(double) * p.n_theta);
     L.inv_sdph = off; off += align_up(sizeof(double) * p.n_theta);
     L.cot = off; off += align_up(sizeof(double) * p.n_theta);
-    L.rest = off; off += align_up(sizeof(double) * NK * p.n_theta);
-    L.rest_f = off; off += align_up(sizeof(float) * NK * p.n_theta);
+    L.rest = off; off += align_up(sizeof(double) * nk * p.n_theta);
+    L.rest_f = off; off += align_up(sizeof(float) * nk * p.n_theta);
     L.dC = off; off += align_up(sizeof(double) * 4 * (p.n_theta + 1));
     L.sI = off; off += align_up(sizeof(double) * (p.n_theta + 1));
     L.fields = off; off += align_up(sizeof(double) * 4 * n);
@@ -1050,8 +1103,10 @@ vlbm_status check_params(const vlbm_params* p) {
         return fail(VLBM_ERR_ARG, "n_phi must be 1 or even");
     if ((long long)p->n_theta * p->n_phi > (1LL << 31) - 1)
         return fail(VLBM_ERR_ARG, "grid too large");
+    if (p->q != 3 && p->q != 4)
+        return fail(VLBM_ERR_UNSUPPORTED, "q = %d: the quadratures are q = 3 (D2Q9) and 4 (D2Q16)", p->q);
     if (p->storage >= 0 && p->storage <= 2 &&
-        (unsigned long long)NK * p->n_theta * p->n_phi * store_bytes(p->storage) > 0xffffffffULL)
+        (unsigned long long)p->q * p->q * p->n_theta * p->n_phi * store_bytes(p->storage) > 0xffffffffULL)
         return fail(VLBM_ERR_UNSUPPORTED,
                     "one population buffer must stay below 4 GiB (32-bit buffer offsets)");
     if (!(p->radius > 0) || !(p->tau > 0) || !(p->dt > 0) || !(p->rho0 > 0) || !(p->weno_eps > 0))
@@ -1059,7 +1114,7 @@ vlbm_status check_params(const vlbm_params* p) {
     if (!std::isfinite(p->radius) || !std::isfinite(p->tau) || !std::isfinite(p->dt) ||
         !std::isfinite(p->rho0) || !std::isfinite(p->weno_eps))
         return fail(VLBM_ERR_ARG, "non-finite parameter");
-    if (p->q != 4) return fail(VLBM_ERR_UNSUPPORTED, "only q = 4 (D2Q16) is implemented");
+
     if (p->storage < 0 || p->storage > 2) return fail(VLBM_ERR_UNSUPPORTED, "unknown storage %d", p->storage);
     if ((p->advection & ~(VLBM_ADV_SCHEME_MASK | VLBM_ADV_KOMISSAROV)) ||
         (p->advection & VLBM_ADV_SCHEME_MASK) > VLBM_ADV_U3)
@@ -1172,6 +1227,7 @@ vlbm_status launch_stage(vlbm_ctx* const* xs, int n, int stage, hipStream_t stre
         const bool wide = xs[c0]->tile == 1;
         bool gen = false;
         for (int i = 0; i < m; ++i) gen = gen || xs[c0 + i]->p.advection != VLBM_ADV_WENO5;
+        const bool d2q9 = xs[c0]->p.q == 3;      // the D2Q9 kernel exists as the general variant
         if (m == 1) {
             RunDesc d[3];
             fill_descs(xs[c0], d);
@@ -1179,8 +1235,12 @@ vlbm_status launch_stage(vlbm_ctx* const* xs, int n, int stage, hipStream_t stre
         }
         // one of the 8 (single/batch x tile x general/specialised) instantiations
         auto go = [&](auto batch, auto tl, auto g) {
-            hipLaunchKernelGGL((stage_kernel<St, decltype(batch)::value, decltype(tl), decltype(g)::value>),
-                               grid, dim3(NTHR), 0, stream, A);
+            if (d2q9)
+                hipLaunchKernelGGL((stage_kernel<St, decltype(batch)::value, decltype(tl), true, 3>),
+                                   grid, dim3(NTHR), 0, stream, A);
+            else
+                hipLaunchKernelGGL((stage_kernel<St, decltype(batch)::value, decltype(tl), decltype(g)::value, 4>),
+                                   grid, dim3(NTHR), 0, stream, A);
         };
         using T_ = std::true_type;
         using F_ = std::false_type;
@@ -1232,6 +1292,8 @@ vlbm_status check_batch(vlbm_ctx* const* xs, int n) {
             return fail(VLBM_ERR_ARG, "contexts of a batch must share the device");
         if (xs[i]->tile != xs[0]->tile)
             return fail(VLBM_ERR_ARG, "contexts of a batch must share the tile shape");
+        if (xs[i]->p.q != xs[0]->p.q)
+            return fail(VLBM_ERR_ARG, "contexts of a batch must share the quadrature order");
         for (int j = 0; j < i; ++j)
             if (xs[j] == xs[i]) return fail(VLBM_ERR_ARG, "context %d appears twice", i);
     }
@@ -1298,14 +1360,9 @@ vlbm_status vlbm_set_tile_shape(vlbm_ctx* x, int rows, int cols) {
 
 vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[2]) {
     if (!v || !w || !residual) return fail(VLBM_ERR_ARG, "NULL output");
-    const quad32::Rule& q = quad32::rule();
-    const float fv[NQ] = {-q.vo, -q.vi, q.vi, q.vo};
-    const float fw[3] = {q.woo, q.woi, q.wii};
-    for (int i = 0; i < NQ; ++i) v[i] = fv[i];
-    for (int k = 0; k < NK; ++k)
-        w[k] = fw[(int)((k >> 2) == 1 || (k >> 2) == 2) + (int)((k & 3) == 1 || (k & 3) == 2)];
-    residual[0] = q.e00;
-    residual[1] = q.e20;
+    quad32::fp32_rule(4, v, w);
+    residual[0] = quad32::rule(4).e00;
+    residual[1] = quad32::rule(4).e20;
     return VLBM_OK;
 }
 
@@ -1327,20 +1384,19 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     x->L = L;
     x->launches = 0;
     x->tile = 0;
-    build_consts(x->c, p->storage);
-    const quad32::Rule& q32 = quad32::rule();
-    const float fv[NQ] = {-q32.vo, -q32.vi, q32.vi, q32.vo};
-    const float fw[3] = {q32.woo, q32.woi, q32.wii};   // by the number of inner nodes of k
-    for (int i = 0; i < NQ; ++i) { x->cd.v[i] = x->c.v[i]; x->cf.v[i] = fv[i]; }
-    for (int k = 0; k < NK; ++k) {
-        const double vw = x->c.v[k >> 2] * x->c.wk[k];
-        const int inner = (int)((k >> 2) == 1 || (k >> 2) == 2) + (int)((k & 3) == 1 || (k & 3) == 2);
-        x->cd.wk[k] = x->c.wk[k]; x->cf.wk[k] = fw[inner];
+    build_consts(x->c, p->storage, p->q);
+    const int q = p->q;
+    float fv[NQMAX] = {}, fw[NKMAX] = {};
+    quad32::fp32_rule(q, fv, fw);
+    for (int i = 0; i < q; ++i) { x->cd.v[i] = x->c.v[i]; x->cf.v[i] = fv[i]; }
+    for (int k = 0; k < q * q; ++k) {
+        const double vw = x->c.v[k / q] * x->c.wk[k];
+        x->cd.wk[k] = x->c.wk[k]; x->cf.wk[k] = fw[k];
         x->cd.vw[k] = vw; x->cf.vw[k] = (float)vw;
         x->cd.scale[k] = x->c.scale[k]; x->cf.scale[k] = (float)x->c.scale[k];
         x->cd.iscale[k] = x->c.iscale[k]; x->cf.iscale[k] = (float)x->c.iscale[k];
     }
-    for (int i = 0; i < NQ * NQ * NQ; ++i) {
+    for (int i = 0; i < q * q * q; ++i) {
         x->cd.fa[i] = x->c.fa[i]; x->cf.fa[i] = (float)x->c.fa[i];
         x->cd.fb[i] = x->c.fb[i]; x->cf.fb[i] = (float)x->c.fb[i];
     }
@@ -1566,17 +1622,19 @@ vlbm_status vlbm_get_populations(vlbm_ctx* x, double* f, int on_dev) {
     const int n = n_cells(x);
     const void* fn = x->ws + x->L.fbuf[0];
     double* F = at<double>(x, x->L.fields);
-    for (int k0 = 0; k0 < NK; k0 += 4) {
+    const int nk = x->p.q * x->p.q;
+    for (int k0 = 0; k0 < nk; k0 += 4) {
+        const int m = nk - k0 < 4 ? nk - k0 : 4;
         double* dst = on_dev ? f + (size_t)k0 * n : F;
         vlbm_status st = dispatch(x->p.storage, [&](auto tag) {
             using St = decltype(tag);
             hipLaunchKernelGGL(decode_kernel<St>, dim3((n + 255) / 256), dim3(256), 0, x->stream, fn,
-                               dst, x->c, n, x->p.rho0, k0, 4);
+                               dst, x->c, n, x->p.rho0, k0, m);
             return launch_check();
         });
         if (st) return st;
         if (!on_dev) {
-            HIP_OK(hipMemcpyAsync(f + (size_t)k0 * n, F, 4 * (size_t)n * sizeof(double),
+            HIP_OK(hipMemcpyAsync(f + (size_t)k0 * n, F, m * (size_t)n * sizeof(double),
                                   hipMemcpyDeviceToHost, x->stream));
             HIP_OK(hipStreamSynchronize(x->stream));
         }
@@ -1589,15 +1647,17 @@ vlbm_status vlbm_set_populations(vlbm_ctx* x, const double* f, int on_dev) {
     const int n = n_cells(x);
     void* fn = x->ws + x->L.fbuf[0];
     double* F = at<double>(x, x->L.fields);
-    for (int k0 = 0; k0 < NK; k0 += 4) {
+    const int nk = x->p.q * x->p.q;
+    for (int k0 = 0; k0 < nk; k0 += 4) {
+        const int m = nk - k0 < 4 ? nk - k0 : 4;
         const double* src = on_dev ? f + (size_t)k0 * n : F;
         if (!on_dev)
-            HIP_OK(hipMemcpyAsync(F, f + (size_t)k0 * n, 4 * (size_t)n * sizeof(double),
+            HIP_OK(hipMemcpyAsync(F, f + (size_t)k0 * n, m * (size_t)n * sizeof(double),
                                   hipMemcpyHostToDevice, x->stream));
         vlbm_status st = dispatch(x->p.storage, [&](auto tag) {
             using St = decltype(tag);
             hipLaunchKernelGGL(encode_kernel<St>, dim3((n + 255) / 256), dim3(256), 0, x->stream, src,
-                               fn, x->c, n, x->p.rho0, k0, 4);
+                               fn, x->c, n, x->p.rho0, k0, m);
             return launch_check();
         });
         if (st) return st;

@@ -227,14 +227,15 @@ class Solver:
     ``torch.cuda.current_stream()`` at construction (or ``stream``)."""
 
     def __init__(self, n_theta, n_phi, tau, dt=None, storage="f64", radius=1.0, rho0=1.0,
-                 weno_eps=1e-6, stream=None, scheme="weno5", komissarov=False):
+                 weno_eps=1e-6, stream=None, scheme="weno5", komissarov=False, q=4):
         import torch
         if not torch.cuda.is_available():
             raise VlbmError("no HIP device visible to torch")
         load()
         self.n_theta, self.n_phi = int(n_theta), int(n_phi)
-        p = make_params(n_theta, n_phi, tau, 1.0, storage, radius, rho0, weno_eps,
+        p = make_params(n_theta, n_phi, tau, 1.0, storage, radius, rho0, weno_eps, q=q,
                         scheme=scheme, komissarov=komissarov)
+        self.q = int(q)
         if dt is None:
             dt = vlbm_suggest_dt(p)
         p.dt = float(dt)
@@ -287,13 +288,13 @@ class Solver:
         return om
 
     def populations(self):
-        f = np.empty((16, self.n_theta, self.n_phi))
+        f = np.empty((self.q * self.q, self.n_theta, self.n_phi))
         vlbm_get_populations(self.ctx, f.ctypes.data, 0)
         return f
 
     def set_populations(self, f):
         f, ptr = _host(f)
-        assert f.shape == (16, self.n_theta, self.n_phi)
+        assert f.shape == (self.q * self.q, self.n_theta, self.n_phi)
         vlbm_set_populations(self.ctx, ptr, 0)
 
     def correct_moments(self, drho, dut, dup):

@@ -57,7 +57,7 @@ def test_invalid_parameters_are_rejected_on_the_host(lib):
     assert B.vlbm_workspace_bytes(p) > 0
     bad = [B.make_params(2, 64, 1e-3, 1e-3), B.make_params(32, 63, 1e-3, 1e-3),
            B.make_params(32, 64, -1.0, 1e-3), B.make_params(32, 64, 1e-3, 0.0),
-           B.make_params(32, 64, 1e-3, 1e-3, q=3)]
+           B.make_params(32, 64, 1e-3, 1e-3, q=5)]
     for q in bad:
         assert B.vlbm_workspace_bytes(q) == 0
     out = ctypes.c_void_p()
