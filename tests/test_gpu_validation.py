@@ -1,0 +1,95 @@
+"""Validation of the GPU vLBM against the paper's independent checks:
+the spherical Riemann problem (Sec. IV.C) against the App. D Euler solver and
+the Rankine-Hugoniot relations, and the isotropy test of App. C (an
+axisymmetric sound mode in a rotated frame)."""
+import numpy as np
+import pytest
+
+from paper_2504_15574_amd import validation as V
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    from paper_2504_15574_amd import load
+    load()
+
+
+def test_riemann_problem_matches_euler_and_rankine_hugoniot():
+    # rho = 1 for theta < pi/10, 0.125 beyond, at rest (Sec. IV.C); N = 512,
+    # tau = 5e-5 (nearly inviscid).  The shock runs at about Mach 1.5.
+    from paper_2504_15574_amd import Solver
+    N, tau = 512, 5e-5
+    th = (np.arange(N) + 0.5) * np.pi / N
+    rho0 = np.where(th < np.pi / 10, 1.0, 0.125)
+    s = Solver(N, 1, tau)
+    s.init_fields(rho0[:, None], np.zeros((N, 1)), np.zeros((N, 1)))
+    snaps = {}
+    for t in (0.2, 0.25):
+        s.step(int(round((t - s.t) / s.dt)))
+        r, a, _ = s.moments(with_T=False)
+        snaps[t] = (r[:, 0].copy(), a[:, 0].copy())
+    assert s.diagnostics()[4] == 0
+    s.close()
+    _, _, E = V.euler_axisym(rho0, np.zeros(N), 0.25, times=(0.25,))
+    f1 = V.shock_front(th, snaps[0.2][0], np.pi / 10)
+    f2 = V.shock_front(th, snaps[0.25][0], np.pi / 10)
+    fe = V.shock_front(th, E[0.25][0], np.pi / 10)
+    dth = np.pi / N
+    print(f"  front: vLBM {f2:.4f}, Euler {fe:.4f} ({(f2 - fe) / dth:+.2f} cells)")
+    assert abs(f2 - fe) < 0.5 * dth
+    L1 = np.abs(snaps[0.25][0] - E[0.25][0]).sum() / np.abs(E[0.25][0]).sum()
+    assert L1 < 5e-3
+    # Rankine-Hugoniot: the front speed predicts the state behind the front
+    rho_n, u_n = V.rh_post_shock((f2 - f1) / 0.05, 0.125)
+    i = np.searchsorted(th, f2 - 0.04)
+    r, u = snaps[0.25]
+    print(f"  RH: rho_N {rho_n:.4f} vs {r[i]:.4f}, u_N {u_n:.4f} vs {u[i]:.4f}")
+    assert rho_n == pytest.approx(r[i], rel=0.04)
+    assert u_n == pytest.approx(u[i], rel=0.02)
+
+
+def test_isotropy_of_a_rotated_sound_mode():
+    # rho = 1 + 1e-3 P2(cos theta) at rest, written in a frame rotated by alpha
+    # about y (App. C) on a 64 x 128 grid, against a 512-row axisymmetric run
+    # mapped into the rotated frame (scalars by position, velocities by eq.
+    # (transf_u)), t = 0.5.  The rotated runs are as accurate as the
+    # grid-aligned one.
+    from paper_2504_15574_amd import Solver
+    p2 = lambda x: 0.5 * (3 * x ** 2 - 1)
+    nt, nph, tau, a0, T = 64, 128, 1e-3, 1e-3, 0.5
+    thp = (np.arange(nt) + 0.5) * np.pi / nt
+    php = (np.arange(nph) + 0.5) * 2 * np.pi / nph
+    TP, PP = np.meshgrid(thp, php, indexing="ij")
+    w = np.sin(TP)
+    errs = {}
+    for alpha in (0.0, 0.6, np.pi / 2):
+        th, ph = V.to_original(TP, PP, alpha)
+        s = Solver(nt, nph, tau)
+        s.init_fields(1 + a0 * p2(np.cos(th)), np.zeros((nt, nph)), np.zeros((nt, nph)))
+        n = int(round(T / s.dt))
+        s.step(n)
+        r, ut, up = s.moments(with_T=False)
+        dt = s.dt
+        s.close()
+        NF = 512
+        thf = (np.arange(NF) + 0.5) * np.pi / NF
+        f = Solver(NF, 1, tau, dt)
+        f.init_fields((1 + a0 * p2(np.cos(thf)))[:, None], np.zeros((NF, 1)), np.zeros((NF, 1)))
+        f.step(n)
+        rf, uf, _ = f.moments(with_T=False)
+        f.close()
+        rr, ur = np.interp(th, thf, rf[:, 0]), np.interp(th, thf, uf[:, 0])
+        ua, ub = V.velocity_to_rotated(th, ph, TP, PP, ur, 0 * ur, alpha)
+        er = np.sqrt((w * (r - rr) ** 2).sum() / (w * (rr - 1) ** 2).sum())
+        eu = np.sqrt((w * ((ut - ua) ** 2 + (up - ub) ** 2)).sum() / (w * (ua ** 2 + ub ** 2)).sum())
+        errs[alpha] = (er, eu)
+        print(f"  alpha {alpha:.2f}: rel L2 rho - 1 {er:.2e}, u {eu:.2e}")
+    for alpha in (0.6, np.pi / 2):
+        assert errs[alpha][0] < 1e-4 and errs[alpha][1] < 1e-4
+        assert errs[alpha][0] < 2 * errs[0.0][0] and errs[alpha][1] < 2 * errs[0.0][1]
