@@ -15,6 +15,7 @@
 // the same operator as on f itself.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -287,11 +288,14 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
     return ((nt + ts - 1) / ts) * ((np + tq - 1) / tq);
 }
 
-// GEN: the general variant (any advection scheme, Komissarov interface factor),
-// launched when a run of the launch needs it; the default WENO-5 standard form
-// uses the specialised variant, which keeps two registers fewer.
-template <class St, bool BATCH, class Tl, bool GEN, int NQ>
+// VAR: 0 the WENO-5 standard form (the default; fewest registers), 1 WENO-5
+// with the interface factor of the Komissarov form (or 1), 2 the upwind
+// fluxes U1/U2/U3 (order read per run) with the interface factor.  A launch
+// covers runs of one variant.
+enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
+template <class St, bool BATCH, class Tl, int VAR, int NQ>
 __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
+    constexpr bool GEN = VAR != VAR_WENO, UPW = VAR == VAR_UPWIND;
     constexpr int NK = NQ * NQ;
     constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, LC = Tl::LC, LT = Tl::LT;
     constexpr int NLOAD = Tl::NLOAD, NFT = Tl::NFT, NFP = Tl::NFP;
@@ -383,10 +387,15 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const int ti = tid / TQ, tc = tid % TQ;
     const int tbase = ti * LC + tc + NGH;                // LDS rows ti .. ti+5
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
-    const T dCp1 = T(D.rows.dC[2 * ig]), dCp3 = T(D.rows.dC[2 * ig + 1]);
-    const T dCm1 = T(D.rows.dC[2 * (nt + 1) + 2 * ig]), dCm3 = T(D.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
+    T dCp1 = T(0), dCp3 = T(0), dCm1 = T(0), dCm3 = T(0);
+    if constexpr (!UPW) {
+        dCp1 = T(D.rows.dC[2 * ig]);
+        dCp3 = T(D.rows.dC[2 * ig + 1]);
+        dCm1 = T(D.rows.dC[2 * (nt + 1) + 2 * ig]);
+        dCm3 = T(D.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
+    }
     const T sIf = GEN ? T(D.rows.sI[ig]) : T(1);         // 1, or sin th at the interface (Komissarov)
-    const int scheme = GEN ? D.scheme : (int)VLBM_ADV_WENO5;
+    const int scheme = UPW ? D.scheme : (int)VLBM_ADV_WENO5;
     // ---- phi interface of this thread: the left face of its cell for the 240
     // cell threads, the right faces of column 15 for threads 240..254
     const bool phas = tid < NFP;
@@ -452,7 +461,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             }
             gself = g[3];                                // this thread's cell (row ti, column tc)
             T F;
-            if (scheme == VLBM_ADV_WENO5) {
+            if constexpr (!UPW) {
                 if (2 * kt >= NQ)                        // v_kt > 0 (zero for the middle Q = 3 node)
                     F = weno5(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4], eps12,
                               vw * dCp1, vw * dCp3);
@@ -472,7 +481,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 #pragma unroll
             for (int m = 0; m < 6; ++m) g[m] = tile[tb][pbase + m];
             T F;
-            if (scheme == VLBM_ADV_WENO5) {
+            if constexpr (!UPW) {
                 if (2 * kp >= NQ)
                     F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
                 else
@@ -1205,55 +1214,70 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
     d[2].gin = fb; d[2].out = fn; d[2].a = 1.0 / 3.0; d[2].b = 2.0 / 3.0;
 }
 
-// One RK stage for n contexts of the same storage format, MAXRUNS per launch.
+// The kernel variant a context's scheme needs.
+template <class St>
+int variant_of(const vlbm_ctx* x) {
+    const int scheme = x->p.advection & VLBM_ADV_SCHEME_MASK;
+    if (scheme != VLBM_ADV_WENO5) return VAR_UPWIND;
+    return (x->p.advection != VLBM_ADV_WENO5 || x->p.q == 3) ? VAR_WENO_GEN : VAR_WENO;
+}
+
+// One launch of one variant over up to MAXRUNS contexts.
+template <class St, int VAR>
+vlbm_status launch_group(vlbm_ctx* const* xs, int m, int stage, hipStream_t stream) {
+    StageArgs A;
+    A.cd = xs[0]->cd;
+    A.cf = xs[0]->cf;
+    A.nruns = m;
+    A.tile_start[0] = 0;
+    for (int i = 0; i < m; ++i) {
+        vlbm_ctx* x = xs[i];
+        A.desc[i] = desc_of(x, stage);
+        A.tile_start[i + 1] = A.tile_start[i] + n_tiles(x->p.n_theta, x->p.n_phi, x->tile);
+        x->launches++;
+    }
+    const int nb = A.tile_start[m];
+    const dim3 grid(8 * ((nb + 7) / 8));
+    const bool wide = xs[0]->tile == 1;
+    const bool d2q9 = xs[0]->p.q == 3;
+    if (m == 1) {
+        RunDesc d[3];
+        fill_descs(xs[0], d);
+        A.run0 = d[stage - 1];
+    }
+    auto go = [&](auto batch, auto tl) {
+        constexpr bool BT = decltype(batch)::value;
+        using TL = decltype(tl);
+        if constexpr (VAR == VAR_WENO) {
+            hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR_WENO, 4>), grid, dim3(NTHR), 0, stream, A);
+        } else {
+            if (d2q9) hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR, 3>), grid, dim3(NTHR), 0, stream, A);
+            else hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR, 4>), grid, dim3(NTHR), 0, stream, A);
+        }
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (m == 1) { if (wide) go(F_{}, Tile7x32{}); else go(F_{}, Tile15x16{}); }
+    else { if (wide) go(T_{}, Tile7x32{}); else go(T_{}, Tile15x16{}); }
+    return launch_check();
+}
+
+// One RK stage for n contexts of the same storage format: one launch per
+// kernel variant present, MAXRUNS contexts per launch.
 template <class St>
 vlbm_status launch_stage(vlbm_ctx* const* xs, int n, int stage, hipStream_t stream) {
     static_assert(sizeof(StageArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
-    for (int c0 = 0; c0 < n; c0 += MAXRUNS) {
-        const int m = n - c0 < MAXRUNS ? n - c0 : MAXRUNS;
-        StageArgs A;
-        A.cd = xs[c0]->cd;
-        A.cf = xs[c0]->cf;
-        A.nruns = m;
-        A.tile_start[0] = 0;
-        for (int i = 0; i < m; ++i) {
-            vlbm_ctx* x = xs[c0 + i];
-            A.desc[i] = desc_of(x, stage);
-            A.tile_start[i + 1] = A.tile_start[i] + n_tiles(x->p.n_theta, x->p.n_phi, x->tile);
-            x->launches++;
+    std::vector<vlbm_ctx*> by[3];
+    for (int i = 0; i < n; ++i) by[variant_of<St>(xs[i])].push_back(xs[i]);
+    for (int v = 0; v < 3; ++v)
+        for (size_t c0 = 0; c0 < by[v].size(); c0 += MAXRUNS) {
+            const int m = (int)std::min<size_t>(MAXRUNS, by[v].size() - c0);
+            vlbm_ctx* const* g = by[v].data() + c0;
+            vlbm_status st = v == VAR_WENO ? launch_group<St, VAR_WENO>(g, m, stage, stream)
+                           : v == VAR_WENO_GEN ? launch_group<St, VAR_WENO_GEN>(g, m, stage, stream)
+                                               : launch_group<St, VAR_UPWIND>(g, m, stage, stream);
+            if (st) return st;
         }
-        const int nb = A.tile_start[m];
-        const dim3 grid(8 * ((nb + 7) / 8));
-        const bool wide = xs[c0]->tile == 1;
-        bool gen = false;
-        for (int i = 0; i < m; ++i) gen = gen || xs[c0 + i]->p.advection != VLBM_ADV_WENO5;
-        const bool d2q9 = xs[c0]->p.q == 3;      // the D2Q9 kernel exists as the general variant
-        if (m == 1) {
-            RunDesc d[3];
-            fill_descs(xs[c0], d);
-            A.run0 = d[stage - 1];
-        }
-        // one of the 8 (single/batch x tile x general/specialised) instantiations
-        auto go = [&](auto batch, auto tl, auto g) {
-            if (d2q9)
-                hipLaunchKernelGGL((stage_kernel<St, decltype(batch)::value, decltype(tl), true, 3>),
-                                   grid, dim3(NTHR), 0, stream, A);
-            else
-                hipLaunchKernelGGL((stage_kernel<St, decltype(batch)::value, decltype(tl), decltype(g)::value, 4>),
-                                   grid, dim3(NTHR), 0, stream, A);
-        };
-        using T_ = std::true_type;
-        using F_ = std::false_type;
-        if (m == 1) {
-            if (wide) { if (gen) go(F_{}, Tile7x32{}, T_{}); else go(F_{}, Tile7x32{}, F_{}); }
-            else { if (gen) go(F_{}, Tile15x16{}, T_{}); else go(F_{}, Tile15x16{}, F_{}); }
-        } else {
-            if (wide) { if (gen) go(T_{}, Tile7x32{}, T_{}); else go(T_{}, Tile7x32{}, F_{}); }
-            else { if (gen) go(T_{}, Tile15x16{}, T_{}); else go(T_{}, Tile15x16{}, F_{}); }
-        }
-        vlbm_status st = launch_check();
-        if (st) return st;
-    }
     return VLBM_OK;
 }
 
