@@ -197,11 +197,15 @@ struct StF16 {
 // function at the points; g: the values of the smoothness indicators (a
 // deviation from a uniform state gives the same indicators).
 //   F = F2 + w1 (F1 - F2) + w3 (F3 - F2),  w_i = (d_i / q_i) / sum_j (d_j / q_j),
-//   q_i = (eps + sigma_i)^2.
-// The indicators are carried scaled by 12 (13 a^2 + 3 b^2 with eps scaled to
-// match), which leaves the normalised weights unchanged, and the weights are
-// normalised with a single reciprocal.  c1, c3 add rest-state candidate
-// differences that share the weights (zero for the phi direction).
+//   q_i = (eps + sigma_i)^2,  d = (1, 6, 3) / 10.
+// Returned scaled by 6 (the caller folds 1/6 into its flux-difference factor):
+//   6F = G2 + q2 (q3 A + 1.5 q1 B) / [q2 (q3 / 2 + 1.5 q1) + 3 q1 q3]
+// with G2 = 6 F2, A = 3 (F1 - F2), B = 6 (F3 - F2); multiplying numerator and
+// denominator of the weights by q1 q2 q3 needs a single reciprocal.  The
+// indicators are carried as a^2 + (3/13) b^2 (12/13 of sigma, with eps scaled
+// to match), which leaves the normalised weights unchanged.  REST: vw c1 and
+// vw c3 add the rest state's candidate differences, which share the weights
+// (theta direction; c1, c3 arrive scaled by 3 and 6).
 template <class T> __device__ __forceinline__ T rcp_(T x);
 template <> __device__ __forceinline__ float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double rcp_<double>(double x) {
@@ -210,23 +214,27 @@ template <> __device__ __forceinline__ double rcp_<double>(double x) {
     return fma(r, e, r);
 }
 
-template <class T>
-__device__ __forceinline__ T weno5(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g2, T g3, T g4,
-                                   T eps12, T c1, T c3) {
-    const T F2 = (T(5) * h2 + T(2) * h3 - h1) * T(1.0 / 6.0);
-    const T d1 = (h0 - h3 + T(3) * (h2 - h1)) * T(1.0 / 3.0);    // F1 - F2
-    const T d3 = (h1 - h4 + T(3) * (h3 - h2)) * T(1.0 / 6.0);    // F3 - F2
+template <class T, bool REST>
+__device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g2, T g3, T g4,
+                                     T epsk, T vw, T c1, T c3) {
+    const T G2 = fma(T(5), h2, fma(T(2), h3, -h1));            // 6 F2
+    T A = fma(T(3), h2 - h1, h0 - h3);                          // 3 (F1 - F2)
+    T B = fma(T(3), h3 - h2, h1 - h4);                          // 6 (F3 - F2)
+    if constexpr (REST) {
+        A = fma(vw, c1, A);
+        B = fma(vw, c3, B);
+    }
     const T D0 = g1 - g0, D1 = g2 - g1, D2 = g3 - g2, D3 = g4 - g3;
     const T a1 = D1 - D0, a2 = D2 - D1, a3 = D3 - D2;
-    const T b1 = a1 + T(2) * D1, b2 = D1 + D2, b3 = a3 - T(2) * D2;
-    const T e1 = eps12 + T(13) * a1 * a1 + T(3) * b1 * b1;
-    const T e2 = eps12 + T(13) * a2 * a2 + T(3) * b2 * b2;
-    const T e3 = eps12 + T(13) * a3 * a3 + T(3) * b3 * b3;
+    const T b1 = fma(T(2), D1, a1), b2 = D1 + D2, b3 = fma(T(-2), D2, a3);
+    const T e1 = fma(a1, a1, fma(T(3.0 / 13.0) * b1, b1, epsk));
+    const T e2 = fma(a2, a2, fma(T(3.0 / 13.0) * b2, b2, epsk));
+    const T e3 = fma(a3, a3, fma(T(3.0 / 13.0) * b3, b3, epsk));
     const T q1 = e1 * e1, q2 = e2 * e2, q3 = e3 * e3;
-    const T n1 = q2 * q3, n3 = T(3) * (q1 * q2);
-    const T den = n1 + n3 + T(6) * (q1 * q3);
-    const T r = rcp_(den);
-    return F2 + r * (n1 * (d1 + c1) + n3 * (d3 + c3));
+    const T u = T(1.5) * q1;
+    const T den = fma(q2, fma(T(0.5), q3, u), (u + u) * q3);
+    const T num = q2 * fma(u, B, q3 * A);
+    return fma(num, rcp_(den), G2);
 }
 
 // Upwind fluxes U1, U2, U3 of eq. (fluxes_U1-3) from the stencil points in
@@ -389,10 +397,10 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
     T dCp1 = T(0), dCp3 = T(0), dCm1 = T(0), dCm3 = T(0);
     if constexpr (!UPW) {
-        dCp1 = T(D.rows.dC[2 * ig]);
-        dCp3 = T(D.rows.dC[2 * ig + 1]);
-        dCm1 = T(D.rows.dC[2 * (nt + 1) + 2 * ig]);
-        dCm3 = T(D.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
+        dCp1 = T(3.0 * D.rows.dC[2 * ig]);
+        dCp3 = T(6.0 * D.rows.dC[2 * ig + 1]);
+        dCm1 = T(3.0 * D.rows.dC[2 * (nt + 1) + 2 * ig]);
+        dCm3 = T(6.0 * D.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
     }
     const T sIf = GEN ? T(D.rows.sI[ig]) : T(1);         // 1, or sin th at the interface (Komissarov)
     const int scheme = UPW ? D.scheme : (int)VLBM_ADV_WENO5;
@@ -410,11 +418,13 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     const bool valid = cell && cs < nt && cq < np;
     const int csc = cs < nt ? cs : nt - 1;
     const T dt = T(D.dt);
-    const T dsth = dt * T(D.rows.inv_sdth[csc]);
-    const T dsph = dt * T(D.rows.inv_sdph[csc]);
+    // the WENO fluxes arrive scaled by 6 (see weno5x6)
+    const double fsc = (VAR == VAR_UPWIND) ? 1.0 : 1.0 / 6.0;
+    const T dsth = T(D.dt * D.rows.inv_sdth[csc] * fsc);
+    const T dsph = T(D.dt * D.rows.inv_sdph[csc] * fsc);
     const T dtcot = dt * T(D.rows.cot[csc]);
     const T dti = dt * T(D.inv_tau);
-    const T eps12 = T(12.0 * D.eps);
+    const T epsk = T(12.0 / 13.0 * D.eps);
     const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
                                         : static_cast<const void*>(D.rest_f);
     const rsrc_t rrest = make_rsrc(rest_t, (uint32_t)(NK * nt * sizeof(T)));
@@ -463,11 +473,11 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             T F;
             if constexpr (!UPW) {
                 if (2 * kt >= NQ)                        // v_kt > 0 (zero for the middle Q = 3 node)
-                    F = weno5(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4], eps12,
-                              vw * dCp1, vw * dCp3);
+                    F = weno5x6<T, true>(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4],
+                                         epsk, vw, dCp1, dCp3);
                 else
-                    F = weno5(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1], eps12,
-                              vw * dCm1, vw * dCm3);
+                    F = weno5x6<T, true>(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1],
+                                         epsk, vw, dCm1, dCm3);
             } else {
                 F = 2 * kt >= NQ ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
             }
@@ -483,9 +493,11 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             T F;
             if constexpr (!UPW) {
                 if (2 * kp >= NQ)
-                    F = weno5(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4], eps12, T(0), T(0));
+                    F = weno5x6<T, false>(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4],
+                                          epsk, T(0), T(0), T(0));
                 else
-                    F = weno5(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1], eps12, T(0), T(0));
+                    F = weno5x6<T, false>(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1],
+                                          epsk, T(0), T(0), T(0));
             } else {
                 F = 2 * kp >= NQ ? upwind(scheme, g[1], g[2], g[3]) : upwind(scheme, g[4], g[3], g[2]);
             }
