@@ -29,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 N_THETA, N_PHI, TAU = 2048, 4096, 1e-5
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 KERNEL_NAME = {"f64": "stage_kernel<StF64>", "f32": "stage_kernel<StF32>", "f16": "stage_kernel<StF16>"}
@@ -58,6 +60,19 @@ def measured_traffic(storage: str):
     # each counter scaled by what it reads for a plain copy of known size
     return 1024.0 * (e["fetch_kib_per_dispatch"] * d["copy_scale_fetch"]
                      + e["write_kib_per_dispatch"] * d["copy_scale_write"])
+
+
+def measured_valu(storage: str):
+    """VALU wave-instructions per stage launch from the committed counter
+    summary (SQ_INSTS_VALU), or None when missing or from another kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_c3_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha256_16") != kernel_source_digest():
+        return None
+    return d.get("per_storage", {}).get(storage, {}).get("valu_wave_insts_per_dispatch")
 
 
 def area_rel_l2(a, b, w):
@@ -338,11 +353,22 @@ def main():
                      "avg_launch_us": round(h["avg_launch_us"], 2),
                      "algorithmic_bytes_per_launch": h["bytes_per_launch"]},
     }
+    valu = measured_valu(head)
+    if valu:
+        # the stage kernel's VALU issue rate: what holds the float kernels (the
+        # HBM fraction above is of the algorithmic population bytes)
+        ach = valu / (h["avg_launch_us"] * 1e-6) / 1e9
+        out["roofline"]["valu"] = {"wave_insts_per_launch": valu, "achieved": round(ach, 1),
+                                   "peak": VALU_PEAK_GINST, "unit": "G wave-instructions/s",
+                                   "frac": round(ach / VALU_PEAK_GINST, 4)}
     per = {}
     for s in storages:
         per[s] = {"mlups": round(res[s]["mlups"], 1), "ms_per_step": round(res[s]["ms_per_step"], 4),
                   "hbm_frac_algorithmic": round(res[s]["achieved_gbs"] / HBM_PEAK_GBS, 4),
                   "avg_launch_us": round(res[s]["avg_launch_us"], 2), "finite": res[s]["finite"]}
+        vs = measured_valu(s)
+        if vs:
+            per[s]["valu_issue_frac"] = round(vs / (res[s]["avg_launch_us"] * 1e-6) / 1e9 / VALU_PEAK_GINST, 4)
     out["per_storage"] = per
     if "f64" in res and "f32" in res:
         out["f32_over_f64_mlups"] = round(res["f32"]["mlups"] / res["f64"]["mlups"], 3)

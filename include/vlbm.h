@@ -156,12 +156,17 @@ double vlbm_suggest_dt(const vlbm_params* params);
 
 /* The FP32 nodes v[4] (ascending) and product weights w[16] (k = 4 k_theta +
  * k_phi) that the FP32 and FP16 storage formats compute with.  They are the
- * D2Q16 Gauss-Hermite rule (App. A) moved by at most 10 ulps so that, evaluated
- * exactly on these FP32 values, sum w - 1 (residual[0]) and sum w v_theta^2 - 1
- * (residual[1]) nearly vanish: plain rounding leaves 2e-8 and 4e-8, and the
- * BGK term would then relax the momentum toward (1 + 4e-8) rho u.  Host only;
- * needs no device.  Errors: VLBM_ERR_ARG (NULL pointer). */
-vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[2]);
+ * D2Q16 Gauss-Hermite rule (App. A) moved by at most 10 ulps (nodes) and 40
+ * ulps (weights) so that, evaluated on these FP32 values, sum w - 1
+ * (residual[0]) is 0 and the fourth moments sum w v_theta^4 - 3 (residual[2])
+ * and sum w v_theta^2 v_phi^2 - 1 (residual[3]) nearly vanish; residual[1] =
+ * sum w v_theta^2 - 1 is absorbed by the equilibrium's coefficients, which the
+ * float kernels derive from these moments so that BGK conserves mass and
+ * momentum on the FP32 rule.  Plain rounding of the FP64 rule misses the
+ * fourth moment by 2e-7.  residual[0] and residual[1] are exact, residual[2]
+ * and residual[3] accurate to 1e-18.  Host only; needs no device.  Errors:
+ * VLBM_ERR_ARG (NULL pointer). */
+vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[4]);
 
 /* ---- ensembles (many independent runs per launch) ---- */
 

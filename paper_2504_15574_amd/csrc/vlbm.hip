@@ -83,8 +83,38 @@ struct Rows {
 // the constants the stage kernel uses, in its arithmetic type
 template <class T>
 struct ConstsT {
-    T v[NQMAX], wk[NKMAX], vw[NKMAX], fa[NQMAX * NKMAX], fb[NQMAX * NKMAX], scale[NKMAX], iscale[NKMAX];
+    T v[NQMAX], wk[NKMAX], fa[NQMAX * NKMAX], fb[NQMAX * NKMAX], scale[NKMAX], iscale[NKMAX];
+    // weight of the rest state's theta flux per unit node speed: w_k in FP64; in
+    // FP32 v_k w_k (FP64 node and weight) over the FP32 node, so that the speed
+    // factor times it reproduces the FP64 product the rest-state tables use
+    T wr[NKMAX];
+    // equilibrium coefficients that make its mass and momentum exact on the
+    // rule's own moments S2 = sum w v^2, S4 = sum w v^4, S22 = sum w vt^2 vp^2
+    T eq_e1;    // 1/S2 - 1 (extra weight of the linear term)
+    T eq_hb;    // -S2/2 (u^2 coefficient of the quadratic term)
+    T eq_g6;    // (S4 + 3 S22)/(12 S2) (u^2 coefficient of the cubic term)
 };
+
+// Per-row constants of the stage kernel in its arithmetic type, computed on the
+// host from the run's dt and velocity nodes (v_o, v_i: the outer and inner
+// node magnitudes; the inner node is 0 for Q = 3).  The WENO-5 variants divide
+// the theta and phi factors by 6 (their fluxes arrive scaled by 6).
+template <class T>
+struct CellRowK {       // cell row s
+    T th_o, th_i;       // v_o, v_i times dt / (R sin th_s dth) (Komissarov: dt / (R (cos - cos)))
+    T ph_o, ph_i;       // v_o, v_i times dt / (R sin th_s dph)
+    T dtcot;            // dt cot(th_s) / R
+    T pad[3];
+};
+template <class T>
+struct FaceRowK {       // theta interface i (between rows i-1 and i)
+    T cp1, cp3;         // 3 and 6 times the rest state's C1 - C2, C3 - C2 (v > 0)
+    T cm1, cm3;         // the same on the mirrored stencil (v < 0)
+    T sI;               // factor of the theta flux (Komissarov: sin th at the interface, else 1)
+    T pad[3];
+};
+// run constants in both arithmetic types (uniform per workgroup: scalar loads)
+enum { U_DTI, U_EPSK, U_OMDTI, U_RHO0, U_A, U_B, U_N };
 
 // One run (context) at one RK stage, in device memory inside the context's
 // workspace; written once at creation.
@@ -100,7 +130,15 @@ struct RunDesc {
     const uint32_t* ctr;  // completed steps (reduced-precision storage: dither phase)
     uint32_t seq;         // 16 * (stage - 1)
     int scheme;           // VLBM_ADV_WENO5 / U1 / U2 / U3
+    const void* rowk;     // CellRowK<T>[nt] of the storage's arithmetic type
+    const void* facek;    // FaceRowK<T>[nt + 1]
+    // dt/tau, 12/13 eps (the scaled WENO epsilon), 1 - dt/tau, rho0, a, b
+    double ud[U_N];
+    float uf[U_N];
 };
+template <class T> __device__ __forceinline__ T uni(const RunDesc& D, int i);
+template <> __device__ __forceinline__ double uni<double>(const RunDesc& D, int i) { return D.ud[i]; }
+template <> __device__ __forceinline__ float uni<float>(const RunDesc& D, int i) { return D.uf[i]; }
 
 // Kernel arguments of a stage launch over the tiles of up to MAXRUNS runs
 // sharing one storage format (one run for vlbm_step).
@@ -213,6 +251,12 @@ template <> __device__ __forceinline__ double rcp_<double>(double x) {
     double e = fma(-x, r, 1.0);      // one Newton step on the hardware estimate
     return fma(r, e, r);
 }
+// 1/x with one Newton step in either type: the hardware FP32 estimate alone is
+// not correctly rounded, and a bias in 1/rho is a bias in u (a small force)
+template <class T> __device__ __forceinline__ T rcp_nr(T x) {
+    const T r = rcp_(x);
+    return fma(r, fma(-x, r, T(1)), r);
+}
 
 template <class T, bool REST>
 __device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g2, T g3, T g4,
@@ -287,6 +331,22 @@ struct TileShape {
     static constexpr int NFP = TS * (TQ + 1);                  // phi interfaces
     static_assert(NFT == NTHR && NFP <= NTHR && NLOAD <= 2 * NTHR && TS * TQ <= NTHR, "tile shape");
 };
+// LDS placement of one tile slot, element (row r, column c) of the LR x LC
+// cross-shaped tile.  A wave of the 15 x 16 tile reads four consecutive rows of
+// 16 elements at once (lanes 16i..16i+15 take row r0 + i).  Row-major with pitch
+// 22, rows r and r+1 share LDS banks for 4-byte values; so 4-byte slots keep the
+// even rows in one block and the odd rows in another, each with pitch 32, the odd
+// block starting 16 elements off modulo 32: the four rows then fill disjoint
+// banks (32 or 64 banks of 4 bytes).  8-byte values (16 lanes per LDS cycle) and
+// the 7 x 32 tile (32 lanes per row) keep the row-major layout.
+template <class Tl, int BYTES>
+struct SlotLayout {
+    static constexpr bool SPLIT = BYTES == 4 && Tl::TQ == 16;
+    static constexpr int OB = SPLIT ? ((Tl::LR + 1) / 2) * 32 + 16 : Tl::LC;   // row 1
+    static constexpr int RS2 = SPLIT ? 32 : 2 * Tl::LC;                         // row r -> r + 2
+    static constexpr int SIZE = SPLIT ? OB + (Tl::LR / 2) * 32 : Tl::LT;
+    __device__ static int at(int r, int c) { return (r & 1) * OB + (r >> 1) * RS2 + c; }
+};
 using Tile15x16 = TileShape<15, 16>;
 using Tile7x32 = TileShape<7, 32>;
 constexpr int TILE_ROWS[2] = {15, 7}, TILE_COLS[2] = {16, 32};
@@ -305,15 +365,16 @@ template <class St, bool BATCH, class Tl, int VAR, int NQ>
 __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     constexpr bool GEN = VAR != VAR_WENO, UPW = VAR == VAR_UPWIND;
     constexpr int NK = NQ * NQ;
-    constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, LC = Tl::LC, LT = Tl::LT;
+    constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR;
     constexpr int NLOAD = Tl::NLOAD, NFT = Tl::NFT, NFP = Tl::NFP;
     using T = typename St::T;
     constexpr int B = St::B;
+    using SL = SlotLayout<Tl, (int)sizeof(T)>;
     constexpr int PAD = 8;                     // destination of the unused load slots
-    __shared__ T tile[3][LT + PAD];            // g of one population, cross-shaped halo
-    __shared__ T tileh[3][LT + PAD];           // theta flux function v sin(theta_j) g_j
+    __shared__ T tile[3][SL::SIZE + PAD];      // g of one population, cross-shaped halo
+    __shared__ T tileh[3][SL::SIZE + PAD];     // theta flux function v sin(theta_j) g_j
     __shared__ T fth[2][NFT];
-    __shared__ T fph[2][NFP + 1];
+    __shared__ T fph[2][NFP + 1];              // faces with phi index < TQ row-major, then the TS right faces
 
     const ConstsT<T>& C = consts_of<T>(A);
     const int tid = threadIdx.x;
@@ -374,7 +435,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             qq = wrap(qq + half, np);
         }
         ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
-        ldst[j] = used ? r * LC + c : LT;
+        ldst[j] = used ? SL::at(r, c) : SL::SIZE;
         la[j] = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
         lm[j] = mir ? ~0u : 0u;
         const int js = s0 + r;                        // sin table index of row s0 - 3 + r
@@ -383,57 +444,56 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     auto gload = [&](int k, int j) -> T {
         return St::bld(rin, (((uint32_t)k * planeB) ^ lm[j]) + la[j], 0, (float)C.iscale[k]);
     };
+    // the velocity nodes are symmetric: population (kt, kp) moves with theta
+    // speed sgn(kt) v_o or sgn(kt) v_i (outer or inner node; Q = 3: v_o or 0)
+    auto vsgn = [](int i) { return 2 * i + 1 < NQ ? -1 : (2 * i + 1 > NQ ? 1 : 0); };
+    auto vouter = [](int i) { return i == 0 || i == NQ - 1; };
     auto lstore = [&](int k, int buf, T v0, T v1) {
-        const T vt = C.v[k / NQ];
         tile[buf][ldst[0]] = v0;
         tile[buf][ldst[1]] = v1;
-        tileh[buf][ldst[0]] = (vt * lsin[0]) * v0;
-        tileh[buf][ldst[1]] = (vt * lsin[1]) * v1;
+        if (vsgn(k / NQ) != 0) {              // theta flux function without its speed
+            tileh[buf][ldst[0]] = lsin[0] * v0;
+            tileh[buf][ldst[1]] = lsin[1] * v1;
+        }
     };
 
     // ---- theta interface of this thread: between tile rows ti-1 and ti, column tc
     const int ti = tid / TQ, tc = tid % TQ;
-    const int tbase = ti * LC + tc + NGH;                // LDS rows ti .. ti+5
+    const int tbase0 = SL::at(ti, tc + NGH);             // LDS rows ti, ti+2, ti+4
+    const int tbase1 = SL::at(ti + 1, tc + NGH);         // LDS rows ti+1, ti+3, ti+5
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
-    T dCp1 = T(0), dCp3 = T(0), dCm1 = T(0), dCm3 = T(0);
-    if constexpr (!UPW) {
-        dCp1 = T(3.0 * D.rows.dC[2 * ig]);
-        dCp3 = T(6.0 * D.rows.dC[2 * ig + 1]);
-        dCm1 = T(3.0 * D.rows.dC[2 * (nt + 1) + 2 * ig]);
-        dCm3 = T(6.0 * D.rows.dC[2 * (nt + 1) + 2 * ig + 1]);
-    }
-    const T sIf = GEN ? T(D.rows.sI[ig]) : T(1);         // 1, or sin th at the interface (Komissarov)
+    const FaceRowK<T> fk = static_cast<const FaceRowK<T>*>(D.facek)[ig];
     const int scheme = UPW ? D.scheme : (int)VLBM_ADV_WENO5;
     // ---- phi interface of this thread: the left face of its cell for the 240
     // cell threads, the right faces of column 15 for threads 240..254
     const bool phas = tid < NFP;
     const int pr = tid < TS * TQ ? tid / TQ : tid - TS * TQ;
     const int pj = tid < TS * TQ ? tid % TQ : TQ;
-    const int pbase = (pr + NGH) * LC + pj;              // LDS columns pj .. pj+5
-    const int pslot = pr * (TQ + 1) + pj;
+    const int pbase = SL::at(pr + NGH, pj);              // LDS columns pj .. pj+5
+    const int pslot = pj < TQ ? pr * TQ + pj : TS * TQ + pr;
     // ---- cell of this thread
     const int cr = tid / TQ, cc = tid % TQ;
     const int cs = s0 + cr, cq = q0 + cc;
     const bool cell = tid < TS * TQ;
     const bool valid = cell && cs < nt && cq < np;
     const int csc = cs < nt ? cs : nt - 1;
-    const T dt = T(D.dt);
-    // the WENO fluxes arrive scaled by 6 (see weno5x6)
-    const double fsc = (VAR == VAR_UPWIND) ? 1.0 : 1.0 / 6.0;
-    const T dsth = T(D.dt * D.rows.inv_sdth[csc] * fsc);
-    const T dsph = T(D.dt * D.rows.inv_sdph[csc] * fsc);
-    const T dtcot = dt * T(D.rows.cot[csc]);
-    const T dti = dt * T(D.inv_tau);
-    const T epsk = T(12.0 / 13.0 * D.eps);
+    const int rslot = cc + 1 < TQ ? cr * TQ + cc + 1 : TS * TQ + cr;   // right face of the cell
+    const CellRowK<T> rk = static_cast<const CellRowK<T>*>(D.rowk)[csc];
+    const T dti = uni<T>(D, U_DTI);
+    const T epsk = uni<T>(D, U_EPSK);
     const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
                                         : static_cast<const void*>(D.rest_f);
     const rsrc_t rrest = make_rsrc(rest_t, (uint32_t)(NK * nt * sizeof(T)));
     const uint32_t rvo = (uint32_t)csc * (uint32_t)sizeof(T);
 
+    // the sums start from the rest state's dt L of the cell's row
     T acc[NK];
     T gk[NK];   // the cell's stage input, kept for the float epilogue
 #pragma unroll
-    for (int k = 0; k < NK; ++k) { acc[k] = T(0); gk[k] = T(0); }
+    for (int k = 0; k < NK; ++k) {
+        acc[k] = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
+        gk[k] = T(0);
+    }
     T drho = T(0), jt = T(0), jp = T(0);
 
     // Ring of three LDS slots: population p lives in slot p % 3.  Its global
@@ -451,73 +511,84 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     for (int k = 0; k < NK; ++k) {
         const int kt = k / NQ, kp = k % NQ;
         const int tb = k % 3, fb = k & 1;
-        T gself, Ftself, Flself = T(0);
+        // theta and phi speeds of this population (zero: no flux in that direction)
+        const int st = vsgn(kt), sp = vsgn(kp);
+        T gself = T(0), Ftself = T(0), Flself = T(0);
         // global loads of population k+2 (written to LDS after the barrier)
         T nx0 = T(0), nx1 = T(0);
         if (k + 2 < NK) {
             nx0 = gload(k + 2, 0);
             nx1 = gload(k + 2, 1);
         }
-        // this population's rest-state row value, consumed after the barrier
-        const T R = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
-        // theta flux of h_j = v sin(theta_j) g_j
-        {
-            const T vw = C.vw[k];
+        // theta flux of sin(theta_j) g_j (the speed multiplies the difference)
+        if (st != 0) {
             T g[6], h[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
-                g[m] = tile[tb][tbase + m * LC];
-                h[m] = tileh[tb][tbase + m * LC];
+                const int a = (m & 1 ? tbase1 : tbase0) + (m >> 1) * SL::RS2;
+                g[m] = tile[tb][a];
+                h[m] = tileh[tb][a];
             }
             gself = g[3];                                // this thread's cell (row ti, column tc)
             T F;
             if constexpr (!UPW) {
-                if (2 * kt >= NQ)                        // v_kt > 0 (zero for the middle Q = 3 node)
+                if (st > 0)
                     F = weno5x6<T, true>(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4],
-                                         epsk, vw, dCp1, dCp3);
+                                         epsk, C.wr[k], fk.cp1, fk.cp3);
                 else
                     F = weno5x6<T, true>(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1],
-                                         epsk, vw, dCm1, dCm3);
+                                         epsk, C.wr[k], fk.cm1, fk.cm3);
             } else {
-                F = 2 * kt >= NQ ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
+                F = st > 0 ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
             }
-            if constexpr (GEN) F *= sIf;
+            if constexpr (GEN) F *= fk.sI;
             fth[fb][tid] = F;
             Ftself = F;                                  // top face of this thread's cell
+        } else {
+            gself = tile[tb][tbase1 + SL::RS2];          // LDS row ti+3
         }
-        // phi flux, h = v g (reconstructed on g, scaled by v)
-        if (phas) {
+        // phi flux of g (the speed multiplies the difference)
+        if (sp != 0 && phas) {
             T g[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) g[m] = tile[tb][pbase + m];
             T F;
             if constexpr (!UPW) {
-                if (2 * kp >= NQ)
+                if (sp > 0)
                     F = weno5x6<T, false>(g[0], g[1], g[2], g[3], g[4], g[0], g[1], g[2], g[3], g[4],
                                           epsk, T(0), T(0), T(0));
                 else
                     F = weno5x6<T, false>(g[5], g[4], g[3], g[2], g[1], g[5], g[4], g[3], g[2], g[1],
                                           epsk, T(0), T(0), T(0));
             } else {
-                F = 2 * kp >= NQ ? upwind(scheme, g[1], g[2], g[3]) : upwind(scheme, g[4], g[3], g[2]);
+                F = sp > 0 ? upwind(scheme, g[1], g[2], g[3]) : upwind(scheme, g[4], g[3], g[2]);
             }
-            Flself = C.v[kp] * F;                        // left face of this thread's cell
-            fph[fb][pslot] = Flself;
+            Flself = F;                                  // left face of this thread's cell
+            fph[fb][pslot] = F;
         }
         __syncthreads();
         if (cell) {
-            const T gc = gself, Ft = Ftself, Fl = Flself;
-            const T Fb = fth[fb][(cr + 1) * TQ + cc];
-            const T Fr = fph[fb][cr * (TQ + 1) + cc + 1];
+            const T gc = gself;
             // FP64 folds the BGK loss -g/tau in here; the float kernels form the
             // whole collision term at the end (see the epilogue)
-            if constexpr (sizeof(T) == 8) acc[k] += (T(1) - dti) * gc + R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
-            else acc[k] += R - dsth * (Fb - Ft) - dsph * (Fr - Fl);
-            const T tg = dtcot * gc;
+            T a = acc[k];
+            if constexpr (sizeof(T) == 8) a = fma(uni<T>(D, U_OMDTI), gc, a);
+            if (st != 0) {                               // - v_theta dt/(R sin th dth) (F_b - F_t)
+                const T Fb = fth[fb][(cr + 1) * TQ + cc];
+                const T f = vouter(kt) ? rk.th_o : rk.th_i;
+                a = fma(st > 0 ? -f : f, Fb - Ftself, a);
+            }
+            if (sp != 0) {                               // - v_phi dt/(R sin th dph) (F_r - F_l)
+                const T Fr = fph[fb][rslot];
+                const T f = vouter(kp) ? rk.ph_o : rk.ph_i;
+                a = fma(sp > 0 ? -f : f, Fr - Flself, a);
+            }
+            acc[k] = a;
+            const T tg = rk.dtcot * gc;
 #pragma unroll
-            for (int a = 0; a < NQ; ++a) {
-                acc[a * NQ + kp] += C.fa[(kp * NQ + a) * NQ + kt] * tg;
-                acc[kt * NQ + a] += C.fb[(kt * NQ + a) * NQ + kp] * tg;
+            for (int b = 0; b < NQ; ++b) {
+                acc[b * NQ + kp] += C.fa[(kp * NQ + b) * NQ + kt] * tg;
+                acc[kt * NQ + b] += C.fb[(kt * NQ + b) * NQ + kp] * tg;
             }
             if constexpr (sizeof(T) != 8) gk[k] = gc;
             drho += gc;
@@ -540,13 +611,45 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 
     if (!valid) return;
 
-    // equilibrium part of BGK from the accumulated moments (eq. (feq_Q=4))
-    const T rho0 = T(D.rho0);
+    // Equilibrium part of BGK from the accumulated moments, eq. (feq_Q=4):
+    // f^eq_k = w_k rho (1 + P(xi_k)), xi_k = v_k . u, P(xi) = xi + (xi^2 - u^2)/2
+    // + xi (xi^2 - 3 u^2)/6 (Q = 3 drops the cubic term, eq. (feq_Q=3)), with
+    // the coefficients 1, 1, 3 taken from the rule's moments (eq_e1, eq_hb,
+    // eq_g6: exact mass and momentum on the FP32 rule).  The mirrored
+    // population NK-1-k has -xi and the same weight, so each pair shares the
+    // even part of P and flips the sign of its odd part, which is formed as
+    // xi + xi (...) so that no rounding scales the linear term.
+    const T rho0 = uni<T>(D, U_RHO0);
     const T rho = rho0 + drho;
-    const T irho = T(1) / rho;
+    const T irho = rcp_nr(rho);
     const T ut = jt * irho, up = jp * irho;
     const T u2 = ut * ut + up * up;
-    const T ca = T(D.a), cb = T(D.b);
+    const T ev0 = C.eq_hb * u2;
+    const T cu = fma(-C.eq_g6, u2, C.eq_e1);
+    // v_o u and v_i u (theta and phi components); the inner node is 0 for Q = 3
+    const T ato = C.v[NQ - 1] * ut, apo = C.v[NQ - 1] * up;
+    const T ati = NQ == 4 ? C.v[NQ / 2] * ut : T(0), api = NQ == 4 ? C.v[NQ / 2] * up : T(0);
+    auto xi_of = [&](int k) {
+        const int kt = k / NQ, kp = k % NQ;
+        const T a = vouter(kt) ? ato : ati, b = vouter(kp) ? apo : api;
+        return (vsgn(kt) < 0 ? -a : a) + (vsgn(kp) < 0 ? -b : b);
+    };
+    // rho (1 + P) - rho0 = drho + rho P for the population and its mirror
+    T tk[NK];
+#pragma unroll
+    for (int k = 0; 2 * k < NK - 1; ++k) {
+        const T xi = xi_of(k);
+        const T x2 = xi * xi;
+        const T base = fma(rho, fma(T(0.5), x2, ev0), drho);
+        T od;
+        if constexpr (NQ == 4) od = fma(xi, fma(x2, T(1.0 / 6.0), cu), xi);
+        else od = fma(xi, C.eq_e1, xi);
+        const T ro = rho * od;
+        tk[k] = base + ro;
+        tk[NK - 1 - k] = base - ro;
+    }
+    if constexpr (NK & 1) tk[NK / 2] = fma(rho, ev0, drho);     // xi = 0
+    const T ca = uni<T>(D, U_A), cb = uni<T>(D, U_B);
     const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
     const rsrc_t rout = make_rsrc(D.out, NK * planeB);
     const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
@@ -554,12 +657,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-            const T vt = C.v[k / NQ], vp = C.v[k % NQ];
-            const T xi = vt * ut + vp * up;
-            // eq. (feq_Q=4); Q = 3 drops the cubic term, eq. (feq_Q=3)
-            T pm1 = xi + T(0.5) * (xi * xi - u2);
-            if constexpr (NQ == 4) pm1 += xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
-            const T y = acc[k] + dti * C.wk[k] * (drho + rho * pm1);
+            const T y = fma(dti * C.wk[k], tk[k], acc[k]);
             T o = cb * y;
             if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
             St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
@@ -590,12 +688,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const T g = gk[k];
-            const T vt = C.v[k / NQ], vp = C.v[k % NQ];
-            const T xi = vt * ut + vp * up;
-            // eq. (feq_Q=4); Q = 3 drops the cubic term, eq. (feq_Q=3)
-            T pm1 = xi + T(0.5) * (xi * xi - u2);
-            if constexpr (NQ == 4) pm1 += xi * (xi * xi - T(3) * u2) * T(1.0 / 6.0);
-            const T inc = acc[k] + dti * (C.wk[k] * (drho + rho * pm1) - g);
+            const T inc = fma(dti, fma(C.wk[k], tk[k], -g), acc[k]);
             // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]
             T d = cb * inc;
             if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
@@ -836,17 +929,26 @@ double hermite(int n, double x) {
 
 // ---------------------------------------------------------------------------
 // FP32 quadrature for the float kernels.  Rounded to FP32, the nodes and
-// weights of the D2Q16 rule miss the identities sum w = 1 and sum w v^2 = 1
-// (App. A) by about 2e-8 and 4e-8.  The BGK term then relaxes the momentum toward
-// (1 + 4e-8) rho u instead of rho u: a small force along u that acts every step
-// and adds up over t / tau relaxation times.  Instead the FP32 nodes v_o =
-// sqrt(3 + sqrt6), v_i = sqrt(3 - sqrt6) and the class weights w_oo, w_oi, w_ii
-// of the product rule are moved by a few ulps, to the values within 10 ulps
-// (w_ii: the nearest floats to the mass identity) for which the two identities,
-// evaluated exactly on the FP32 values, hold best: among the candidates with
-// |sum w - 1| <= 2e-9 the one with the smallest |sum w v^2 - 1|, ties broken
-// by the fewest ulps moved.  Exact arithmetic: every product of three floats
-// is an integer multiple of 2^-100 below 2^127.
+// weights of the D2Q16 rule miss the moment identities of App. A (sum w = 1,
+// sum w v^2 = 1, sum w v^4 = 3, sum w v_t^2 v_p^2 = 1) by 1e-8 .. 1e-7.  The
+// BGK term then relaxes the mass and momentum toward slightly wrong values: a
+// small force that acts every step and adds up over t / tau relaxation times.
+// Two measures remove it:
+//  - the FP32 nodes v_o = sqrt(3 + sqrt6), v_i = sqrt(3 - sqrt6) and the class
+//    weights w_oo, w_oi, w_ii of the product rule are moved by a few ulps (nodes
+//    10, weights 40; w_ii: the nearest floats to the mass identity): among the
+//    candidates with sum w = 1 exactly, the one with the smallest
+//    max(|S4 - 3|, 3 |S22 - 1|, |S4 - 3 S22|), S4 = sum w v_t^4, S22 = sum w
+//    v_t^2 v_p^2 (about 2e-8 each, 2e-7 for the nearest floats);
+//  - the equilibrium takes its coefficients from the rule's own moments (S2 =
+//    sum w v_t^2): P(xi) = (1/S2) xi + (xi^2 - S2 u^2)/2 + xi (xi^2 - g u^2)/6
+//    with g = (S4 + 3 S22) / (2 S2), which makes the mass and momentum of the
+//    equilibrium exact for every u up to the remaining anisotropy S4 - 3 S22
+//    (cubic in u).  For the FP64 rule these coefficients are 1, 1 and 3 up to
+//    rounding.
+// The mass and second-moment sums are evaluated exactly: every product of
+// three floats is an integer multiple of 2^-100 below 2^127; the fourth moments
+// in long double.
 namespace quad32 {
 constexpr int FXS = 100;
 using i128 = __int128;
@@ -871,6 +973,7 @@ double to_d(i128 x) { return std::ldexp((double)x, -FXS); }
 struct Rule {
     float vo, vi, woo, woi, wii;
     double e00, e20;
+    long double s2, s4, s22;
 };
 // n_out, n_in: outer and inner nodes per axis (Q = 4: 2 and 2; Q = 3: the
 // nodes +-sqrt3 and the node 0, which stays exactly 0).  A population with m
@@ -885,19 +988,20 @@ Rule search(int q) {
         return (q == 4 ? 24.0 : 6.0) / (h * h);
     };
     const double wo = w1(vo), wi = w1(vi);
-    const i128 one = (i128)1 << FXS, lim00 = (i128)(2e-9 * std::ldexp(1.0, FXS));
-    constexpr int KU = 10;
+    const i128 one = (i128)1 << FXS;
+    constexpr int KU = 10, KW = 40;
     const int KI = q == 4 ? KU : 0;        // the zero node is exact
     Rule best{};
-    i128 best20 = -1;
-    int bestmove = 0;
+    double bestsc = -1;
     for (int a = -KU; a <= KU; ++a) {
         const float fvo = step_ulps((float)vo, a);
+        const long double vo2 = (long double)fvo * fvo, vo4 = vo2 * vo2;
         for (int b = -KI; b <= KI; ++b) {
             const float fvi = step_ulps((float)vi, b);
-            for (int c = -KU; c <= KU; ++c) {
+            const long double vi2 = (long double)fvi * fvi, vi4 = vi2 * vi2;
+            for (int c = -KW; c <= KW; ++c) {
                 const float woo = step_ulps((float)(wo * wo), c);
-                for (int d = -KU; d <= KU; ++d) {
+                for (int d = -KW; d <= KW; ++d) {
                     const float woi = step_ulps((float)(wo * wi), d);
                     const float c0 = (float)((1.0 - n_out * n_out * (double)woo -
                                               2.0 * n_out * n_in * (double)woi) / (n_in * n_in));
@@ -905,18 +1009,23 @@ Rule search(int q) {
                         const float wii = step_ulps(c0, e);
                         const i128 e00 = n_out * n_out * exact(woo) + 2 * n_out * n_in * exact(woi) +
                                          n_in * n_in * exact(wii) - one;
-                        if (e00 > lim00 || -e00 > lim00) continue;
-                        // sum_k w_k v_theta^2 = n_out v_o^2 (n_out w_oo + n_in w_oi)
-                        //                     + n_in v_i^2 (n_out w_oi + n_in w_ii)
-                        const i128 s20 = n_out * (n_out * exact(woo, fvo, fvo) + n_in * exact(woi, fvo, fvo)) +
-                                         n_in * (n_out * exact(woi, fvi, fvi) + n_in * exact(wii, fvi, fvi));
-                        i128 e20 = s20 - one;
-                        if (e20 < 0) e20 = -e20;
-                        const int move = std::abs(a) + std::abs(b) + std::abs(c) + std::abs(d);
-                        if (best20 < 0 || e20 < best20 || (e20 == best20 && move < bestmove)) {
-                            best20 = e20;
-                            bestmove = move;
+                        if (e00 != 0) continue;
+                        const long double s4 = n_out * vo4 * (n_out * (long double)woo + n_in * (long double)woi) +
+                                               n_in * vi4 * (n_out * (long double)woi + n_in * (long double)wii);
+                        const long double s22 = n_out * n_out * (long double)woo * vo4 +
+                                                2 * n_out * n_in * (long double)woi * vo2 * vi2 +
+                                                n_in * n_in * (long double)wii * vi4;
+                        const double e40 = (double)(s4 - 3), e22 = (double)(s22 - 1);
+                        const double sc = std::fmax(std::fmax(std::fabs(e40), 3 * std::fabs(e22)),
+                                                    std::fabs(e40 - 3 * e22));
+                        if (bestsc < 0 || sc < bestsc) {
+                            const i128 s20 = n_out * (n_out * exact(woo, fvo, fvo) + n_in * exact(woi, fvo, fvo)) +
+                                             n_in * (n_out * exact(woi, fvi, fvi) + n_in * exact(wii, fvi, fvi));
+                            bestsc = sc;
                             best = Rule{fvo, fvi, woo, woi, wii, to_d(e00), to_d(s20 - one)};
+                            best.s2 = 1.0L + (long double)to_d(s20 - one);
+                            best.s4 = s4;
+                            best.s22 = s22;
                         }
                     }
                 }
@@ -1088,7 +1197,8 @@ size_t store_bytes(int storage) {
 constexpr int RED_BLOCKS = 1024;
 
 struct Layout {
-    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, sI, fields, part, dout, desc, ctr, total;
+    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, sI, rowk, rowk_f, facek, facek_f;
+    size_t fields, part, dout, desc, ctr, total;
 };
 
 Layout layout_of(const vlbm_params& p) {
@@ -1106,6 +1216,10 @@ Layout layout_of(const vlbm_params& p) {
     L.rest_f = off; off += align_up(sizeof(float) * nk * p.n_theta);
     L.dC = off; off += align_up(sizeof(double) * 4 * (p.n_theta + 1));
     L.sI = off; off += align_up(sizeof(double) * (p.n_theta + 1));
+    L.rowk = off; off += align_up(sizeof(CellRowK<double>) * p.n_theta);
+    L.rowk_f = off; off += align_up(sizeof(CellRowK<float>) * p.n_theta);
+    L.facek = off; off += align_up(sizeof(FaceRowK<double>) * (p.n_theta + 1));
+    L.facek_f = off; off += align_up(sizeof(FaceRowK<float>) * (p.n_theta + 1));
     L.fields = off; off += align_up(sizeof(double) * 4 * n);
     L.part = off; off += align_up(sizeof(double) * 8 * RED_BLOCKS);
     L.dout = off; off += align_up(sizeof(double) * 8);
@@ -1220,10 +1334,25 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
         D.gn = fn;
         D.ctr = at<uint32_t>(x, x->L.ctr);
         D.seq = 16u * (uint32_t)i;
+        const bool f64 = x->p.storage == VLBM_STORE_F64;
+        D.rowk = f64 ? static_cast<const void*>(at<CellRowK<double>>(x, x->L.rowk))
+                     : static_cast<const void*>(at<CellRowK<float>>(x, x->L.rowk_f));
+        D.facek = f64 ? static_cast<const void*>(at<FaceRowK<double>>(x, x->L.facek))
+                      : static_cast<const void*>(at<FaceRowK<float>>(x, x->L.facek_f));
     }
     d[0].gin = fn; d[0].out = fa; d[0].a = 0.0;       d[0].b = 1.0;
     d[1].gin = fa; d[1].out = fb; d[1].a = 0.75;      d[1].b = 0.25;
     d[2].gin = fb; d[2].out = fn; d[2].a = 1.0 / 3.0; d[2].b = 2.0 / 3.0;
+    for (int i = 0; i < 3; ++i) {
+        RunDesc& D = d[i];
+        D.ud[U_DTI] = D.dt * D.inv_tau;
+        D.ud[U_EPSK] = 12.0 / 13.0 * D.eps;
+        D.ud[U_OMDTI] = 1.0 - D.ud[U_DTI];
+        D.ud[U_RHO0] = D.rho0;
+        D.ud[U_A] = D.a;
+        D.ud[U_B] = D.b;
+        for (int j = 0; j < U_N; ++j) D.uf[j] = (float)D.ud[j];
+    }
 }
 
 // The kernel variant a context's scheme needs.
@@ -1394,11 +1523,14 @@ vlbm_status vlbm_set_tile_shape(vlbm_ctx* x, int rows, int cols) {
     return fail(VLBM_ERR_UNSUPPORTED, "tile shape %dx%d (supported: 15x16, 7x32)", rows, cols);
 }
 
-vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[2]) {
+vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[4]) {
     if (!v || !w || !residual) return fail(VLBM_ERR_ARG, "NULL output");
     quad32::fp32_rule(4, v, w);
-    residual[0] = quad32::rule(4).e00;
-    residual[1] = quad32::rule(4).e20;
+    const quad32::Rule& r = quad32::rule(4);
+    residual[0] = r.e00;
+    residual[1] = r.e20;
+    residual[2] = (double)(r.s4 - 3.0L);
+    residual[3] = (double)(r.s22 - 1.0L);
     return VLBM_OK;
 }
 
@@ -1425,10 +1557,26 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     float fv[NQMAX] = {}, fw[NKMAX] = {};
     quad32::fp32_rule(q, fv, fw);
     for (int i = 0; i < q; ++i) { x->cd.v[i] = x->c.v[i]; x->cf.v[i] = fv[i]; }
+    {
+        // moments of the FP64 rule and of the FP32 rule, evaluated exactly enough
+        long double d2 = 0, d4 = 0, d22 = 0;
+        for (int k = 0; k < q * q; ++k) {
+            const long double a = x->c.v[k / q], b = x->c.v[k % q], wk = x->c.wk[k];
+            d2 += wk * a * a; d4 += wk * a * a * a * a; d22 += wk * a * a * b * b;
+        }
+        const quad32::Rule& r = quad32::rule(q);
+        x->cd.eq_e1 = (double)(1.0L / d2 - 1.0L);
+        x->cd.eq_hb = (double)(-0.5L * d2);
+        x->cd.eq_g6 = (double)((d4 + 3.0L * d22) / (12.0L * d2));
+        x->cf.eq_e1 = (float)(1.0L / r.s2 - 1.0L);
+        x->cf.eq_hb = (float)(-0.5L * r.s2);
+        x->cf.eq_g6 = (float)((r.s4 + 3.0L * r.s22) / (12.0L * r.s2));
+    }
     for (int k = 0; k < q * q; ++k) {
         const double vw = x->c.v[k / q] * x->c.wk[k];
         x->cd.wk[k] = x->c.wk[k]; x->cf.wk[k] = fw[k];
-        x->cd.vw[k] = vw; x->cf.vw[k] = (float)vw;
+        x->cd.wr[k] = x->c.wk[k];
+        x->cf.wr[k] = fv[k / q] != 0.f ? (float)(vw / (double)fv[k / q]) : 0.f;
         x->cd.scale[k] = x->c.scale[k]; x->cf.scale[k] = (float)x->c.scale[k];
         x->cd.iscale[k] = x->c.iscale[k]; x->cf.iscale[k] = (float)x->c.iscale[k];
     }
@@ -1439,6 +1587,29 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     HostRows h;
     build_rows(h, *p, x->c);
     std::vector<float> rest_f(h.rest.begin(), h.rest.end());
+    // the stage kernel's per-row constants in both arithmetic types
+    const int nt = p->n_theta;
+    const double fsc = (p->advection & VLBM_ADV_SCHEME_MASK) == VLBM_ADV_WENO5 ? 1.0 / 6.0 : 1.0;
+    const double vod = x->c.v[q - 1], vid = q == 4 ? x->c.v[q / 2] : 0.0;
+    const double vof = fv[q - 1], vif = q == 4 ? fv[q / 2] : 0.0;
+    std::vector<CellRowK<double>> rkd(nt);
+    std::vector<CellRowK<float>> rkf(nt);
+    for (int s = 0; s < nt; ++s) {
+        const double dth = p->dt * h.inv_sdth[s] * fsc, dph = p->dt * h.inv_sdph[s] * fsc;
+        const double dc = p->dt * h.cot[s];
+        rkd[s] = {vod * dth, vid * dth, vod * dph, vid * dph, dc, {0.0, 0.0, 0.0}};
+        rkf[s] = {(float)(vof * dth), (float)(vif * dth), (float)(vof * dph), (float)(vif * dph),
+                  (float)dc, {0.f, 0.f, 0.f}};
+    }
+    std::vector<FaceRowK<double>> fkd(nt + 1);
+    std::vector<FaceRowK<float>> fkf(nt + 1);
+    for (int i = 0; i <= nt; ++i) {
+        const double* pp = &h.dC[2 * i];
+        const double* pm = &h.dC[2 * (nt + 1) + 2 * i];
+        fkd[i] = {3.0 * pp[0], 6.0 * pp[1], 3.0 * pm[0], 6.0 * pm[1], h.sI[i], {0.0, 0.0, 0.0}};
+        fkf[i] = {(float)(3.0 * pp[0]), (float)(6.0 * pp[1]), (float)(3.0 * pm[0]),
+                  (float)(6.0 * pm[1]), (float)h.sI[i], {0.f, 0.f, 0.f}};
+    }
     hipError_t e = hipGetDevice(&x->device);
     const struct { size_t off; const std::vector<double>* v; } up[] = {
         {L.sinv, &h.sinv}, {L.inv_sdth, &h.inv_sdth}, {L.inv_sdph, &h.inv_sdph},
@@ -1451,6 +1622,14 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     if (e == hipSuccess)
         e = hipMemcpyAsync(x->ws + L.rest_f, rest_f.data(), rest_f.size() * sizeof(float),
                            hipMemcpyHostToDevice, x->stream);
+    const struct { size_t off; const void* src; size_t bytes; } upk[] = {
+        {L.rowk, rkd.data(), rkd.size() * sizeof(rkd[0])},
+        {L.rowk_f, rkf.data(), rkf.size() * sizeof(rkf[0])},
+        {L.facek, fkd.data(), fkd.size() * sizeof(fkd[0])},
+        {L.facek_f, fkf.data(), fkf.size() * sizeof(fkf[0])}};
+    for (const auto& u : upk)
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(x->ws + u.off, u.src, u.bytes, hipMemcpyHostToDevice, x->stream);
     RunDesc descs[3];
     fill_descs(x, descs);
     const uint32_t zero = 0;

@@ -115,11 +115,12 @@ def vlbm_suggest_dt(p: vlbm_params) -> float:
 
 
 def vlbm_quadrature_f32():
-    """FP32 nodes (4), product weights (16) and the residuals of sum w = 1 and
-    sum w v_theta^2 = 1 on those FP32 values."""
+    """FP32 nodes (4), product weights (16) and the residuals of sum w = 1,
+    sum w v_theta^2 = 1, sum w v_theta^4 = 3 and sum w v_theta^2 v_phi^2 = 1 on
+    those FP32 values."""
     v = np.zeros(4, np.float32)
     w = np.zeros(16, np.float32)
-    r = np.zeros(2)
+    r = np.zeros(4)
     _check(load().vlbm_quadrature_f32(v.ctypes.data, w.ctypes.data, r.ctypes.data_as(_dp)),
            "vlbm_quadrature_f32")
     return v, w, r
