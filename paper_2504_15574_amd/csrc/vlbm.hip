@@ -299,6 +299,10 @@ __device__ __forceinline__ int wrap(int q, int np) {
     int r = q % np;
     return r < 0 ? r + np : r;
 }
+// the same for q in [-np, 2 np)
+__device__ __forceinline__ int wrap1(int q, int np) {
+    return q < 0 ? q + np : (q >= np ? q - np : q);
+}
 
 // ---------------------------------------------------------------------------
 // Fused RK stage.
@@ -423,16 +427,18 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             r = e2 / NGH + NGH;
             c = (e < TS * NGH) ? e2 % NGH : TQ + NGH + e2 % NGH;
         }
-        int ss = s0 - NGH + r, qq = wrap(q0 - NGH + c, np);
+        // column q0 - 3 + c lies in [-3, np + TQ + 2]: one fold suffices when np >= TQ + 3
+        int ss = s0 - NGH + r;
+        int qq = np >= TQ + NGH ? wrap1(q0 - NGH + c, np) : wrap(q0 - NGH + c, np);
         bool mir = false;
         if (ss < 0) {                   // north pole: row -m <- row m-1 at phi + pi, v -> -v
             ss = -1 - ss;
             mir = true;
-            qq = wrap(qq + half, np);
+            qq = wrap1(qq + half, np);
         } else if (ss >= nt) {          // south pole: row nt-1+m <- row nt-m
             ss = 2 * nt - 1 - ss;
             mir = true;
-            qq = wrap(qq + half, np);
+            qq = wrap1(qq + half, np);
         }
         ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
         ldst[j] = used ? SL::at(r, c) : SL::SIZE;
@@ -467,7 +473,9 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
     // ---- phi interface of this thread: the left face of its cell for the 240
     // cell threads, the right faces of column 15 for threads 240..254
     const bool phas = tid < NFP;
-    const int pr = tid < TS * TQ ? tid / TQ : tid - TS * TQ;
+    // (the idle threads past NFP evaluate a copy of the last right face: every
+    // thread runs the same code and only the faces' owners store)
+    const int pr = tid < TS * TQ ? tid / TQ : min(tid - TS * TQ, TS - 1);
     const int pj = tid < TS * TQ ? tid % TQ : TQ;
     const int pbase = SL::at(pr + NGH, pj);              // LDS columns pj .. pj+5
     const int pslot = pj < TQ ? pr * TQ + pj : TS * TQ + pr;
@@ -548,7 +556,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
             gself = tile[tb][tbase1 + SL::RS2];          // LDS row ti+3
         }
         // phi flux of g (the speed multiplies the difference)
-        if (sp != 0 && phas) {
+        if (sp != 0) {
             T g[6];
 #pragma unroll
             for (int m = 0; m < 6; ++m) g[m] = tile[tb][pbase + m];
@@ -564,7 +572,7 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
                 F = sp > 0 ? upwind(scheme, g[1], g[2], g[3]) : upwind(scheme, g[4], g[3], g[2]);
             }
             Flself = F;                                  // left face of this thread's cell
-            fph[fb][pslot] = F;
+            if (phas) fph[fb][pslot] = F;
         }
         __syncthreads();
         if (cell) {
