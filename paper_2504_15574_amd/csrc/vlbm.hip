@@ -113,6 +113,8 @@ struct FaceRowK {       // theta interface i (between rows i-1 and i)
     T sI;               // factor of the theta flux (Komissarov: sin th at the interface, else 1)
     T pad[3];
 };
+// SSP-RK3 (Sec. III.G): stage i writes a_i g_n + b_i (g_in + dt L(g_in))
+constexpr double RK_A[3] = {0.0, 0.75, 1.0 / 3.0}, RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
 // run constants in both arithmetic types (uniform per workgroup: scalar loads)
 enum { U_DTI, U_EPSK, U_OMDTI, U_RHO0, U_A, U_B, U_N };
 
@@ -123,16 +125,17 @@ struct RunDesc {
     const void* gn;       // f_n deviations (point reads), may alias out
     void* out;            // stage output
     Rows rows;
-    const float* rest_f;  // rest[] in FP32 for the float kernels
+    const float* rest_f;  // rest[] times this stage's b, in FP32, for the float kernels
     int nt, np;
     double dt, inv_tau, rho0, eps;
     double a, b;          // out = a g_n + b (g_in + dt L)
     const uint32_t* ctr;  // completed steps (reduced-precision storage: dither phase)
     uint32_t seq;         // 16 * (stage - 1)
     int scheme;           // VLBM_ADV_WENO5 / U1 / U2 / U3
-    const void* rowk;     // CellRowK<T>[nt] of the storage's arithmetic type
+    const void* rowk;     // CellRowK<T>[nt] of the storage's arithmetic type (float: times b)
     const void* facek;    // FaceRowK<T>[nt + 1]
-    // dt/tau, 12/13 eps (the scaled WENO epsilon), 1 - dt/tau, rho0, a, b
+    // dt/tau, 12/13 eps (the scaled WENO epsilon), 1 - dt/tau, rho0, a, b;
+    // uf[U_DTI] is b dt/tau (the float kernels fold b into the increment)
     double ud[U_N];
     float uf[U_N];
 };
@@ -194,11 +197,13 @@ struct StF32 {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
     }
     // store g + d rounded with a dither x * 2^-32 ulp(g), x in [-2^31, 2^31):
-    // ulp(g) = 2^(E - 150) for the biased exponent E of g (zero and subnormal g
-    // get a dither that underflows to zero)
+    // ulp(g) = 2^(E - 150) for the biased exponent E of g, so the dither is x
+    // times 2^(E - 182), the float whose exponent field is E - 55 (a saturating
+    // subtraction: |g| < 2^-72 gets no dither)
     __device__ static void bst_dither(rsrc_t r, uint32_t vo, uint32_t so, T g, T d, float x, float) {
-        const int E = (int)((__builtin_bit_cast(uint32_t, g) >> 23) & 0xffu);
-        const T v = g + (d + __builtin_ldexpf(x, E - 182));
+        const uint32_t eb = __builtin_bit_cast(uint32_t, g) & 0x7f800000u;
+        const float s = __builtin_bit_cast(float, __builtin_elementwise_sub_sat(eb, 55u << 23));
+        const T v = g + fma(x, s, d);
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
     }
 };
@@ -696,9 +701,9 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const T g = gk[k];
-            const T inc = fma(dti, fma(C.wk[k], tk[k], -g), acc[k]);
-            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]
-            T d = cb * inc;
+            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
+            // kernels' row factors, rest table and dt/tau come multiplied by b
+            T d = fma(dti, fma(C.wk[k], tk[k], -g), acc[k]);
             if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
             const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
             St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
@@ -1221,11 +1226,11 @@ Layout layout_of(const vlbm_params& p) {
     L.inv_sdph = off; off += align_up(sizeof(double) * p.n_theta);
     L.cot = off; off += align_up(sizeof(double) * p.n_theta);
     L.rest = off; off += align_up(sizeof(double) * nk * p.n_theta);
-    L.rest_f = off; off += align_up(sizeof(float) * nk * p.n_theta);
+    L.rest_f = off; off += 3 * align_up(sizeof(float) * nk * p.n_theta);    // per stage
     L.dC = off; off += align_up(sizeof(double) * 4 * (p.n_theta + 1));
     L.sI = off; off += align_up(sizeof(double) * (p.n_theta + 1));
     L.rowk = off; off += align_up(sizeof(CellRowK<double>) * p.n_theta);
-    L.rowk_f = off; off += align_up(sizeof(CellRowK<float>) * p.n_theta);
+    L.rowk_f = off; off += 3 * align_up(sizeof(CellRowK<float>) * p.n_theta);   // per stage
     L.facek = off; off += align_up(sizeof(FaceRowK<double>) * (p.n_theta + 1));
     L.facek_f = off; off += align_up(sizeof(FaceRowK<float>) * (p.n_theta + 1));
     L.fields = off; off += align_up(sizeof(double) * 4 * n);
@@ -1332,7 +1337,7 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
         D.rows.dC = at<double>(x, x->L.dC);
         D.rows.sI = at<double>(x, x->L.sI);
         D.scheme = x->p.advection & VLBM_ADV_SCHEME_MASK;
-        D.rest_f = at<float>(x, x->L.rest_f);
+        D.rest_f = at<float>(x, x->L.rest_f + i * align_up(sizeof(float) * x->p.q * x->p.q * x->p.n_theta));
         D.nt = x->p.n_theta;
         D.np = x->p.n_phi;
         D.dt = x->p.dt;
@@ -1344,13 +1349,15 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
         D.seq = 16u * (uint32_t)i;
         const bool f64 = x->p.storage == VLBM_STORE_F64;
         D.rowk = f64 ? static_cast<const void*>(at<CellRowK<double>>(x, x->L.rowk))
-                     : static_cast<const void*>(at<CellRowK<float>>(x, x->L.rowk_f));
+                     : static_cast<const void*>(at<CellRowK<float>>(
+                           x, x->L.rowk_f + i * align_up(sizeof(CellRowK<float>) * x->p.n_theta)));
         D.facek = f64 ? static_cast<const void*>(at<FaceRowK<double>>(x, x->L.facek))
                       : static_cast<const void*>(at<FaceRowK<float>>(x, x->L.facek_f));
     }
-    d[0].gin = fn; d[0].out = fa; d[0].a = 0.0;       d[0].b = 1.0;
-    d[1].gin = fa; d[1].out = fb; d[1].a = 0.75;      d[1].b = 0.25;
-    d[2].gin = fb; d[2].out = fn; d[2].a = 1.0 / 3.0; d[2].b = 2.0 / 3.0;
+    d[0].gin = fn; d[0].out = fa;
+    d[1].gin = fa; d[1].out = fb;
+    d[2].gin = fb; d[2].out = fn;
+    for (int i = 0; i < 3; ++i) { d[i].a = RK_A[i]; d[i].b = RK_B[i]; }
     for (int i = 0; i < 3; ++i) {
         RunDesc& D = d[i];
         D.ud[U_DTI] = D.dt * D.inv_tau;
@@ -1360,6 +1367,7 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
         D.ud[U_A] = D.a;
         D.ud[U_B] = D.b;
         for (int j = 0; j < U_N; ++j) D.uf[j] = (float)D.ud[j];
+        D.uf[U_DTI] = (float)(D.b * D.ud[U_DTI]);
     }
 }
 
@@ -1594,20 +1602,26 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     }
     HostRows h;
     build_rows(h, *p, x->c);
-    std::vector<float> rest_f(h.rest.begin(), h.rest.end());
+    // float kernels: the rest table and row factors of stage i times its b
+    std::vector<float> rest_f(3 * h.rest.size());
+    for (int i = 0; i < 3; ++i)
+        for (size_t j = 0; j < h.rest.size(); ++j) rest_f[i * h.rest.size() + j] = (float)(RK_B[i] * h.rest[j]);
     // the stage kernel's per-row constants in both arithmetic types
     const int nt = p->n_theta;
     const double fsc = (p->advection & VLBM_ADV_SCHEME_MASK) == VLBM_ADV_WENO5 ? 1.0 / 6.0 : 1.0;
     const double vod = x->c.v[q - 1], vid = q == 4 ? x->c.v[q / 2] : 0.0;
     const double vof = fv[q - 1], vif = q == 4 ? fv[q / 2] : 0.0;
     std::vector<CellRowK<double>> rkd(nt);
-    std::vector<CellRowK<float>> rkf(nt);
+    std::vector<CellRowK<float>> rkf(3 * nt);
     for (int s = 0; s < nt; ++s) {
         const double dth = p->dt * h.inv_sdth[s] * fsc, dph = p->dt * h.inv_sdph[s] * fsc;
         const double dc = p->dt * h.cot[s];
         rkd[s] = {vod * dth, vid * dth, vod * dph, vid * dph, dc, {0.0, 0.0, 0.0}};
-        rkf[s] = {(float)(vof * dth), (float)(vif * dth), (float)(vof * dph), (float)(vif * dph),
-                  (float)dc, {0.f, 0.f, 0.f}};
+        for (int i = 0; i < 3; ++i) {
+            const double b = RK_B[i];
+            rkf[i * nt + s] = {(float)(b * vof * dth), (float)(b * vif * dth), (float)(b * vof * dph),
+                               (float)(b * vif * dph), (float)(b * dc), {0.f, 0.f, 0.f}};
+        }
     }
     std::vector<FaceRowK<double>> fkd(nt + 1);
     std::vector<FaceRowK<float>> fkf(nt + 1);
@@ -1627,12 +1641,18 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
         e = hipMemcpyAsync(x->ws + u.off, u.v->data(), u.v->size() * sizeof(double),
                            hipMemcpyHostToDevice, x->stream);
     }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(x->ws + L.rest_f, rest_f.data(), rest_f.size() * sizeof(float),
-                           hipMemcpyHostToDevice, x->stream);
+    // the per-stage float tables sit 256-byte aligned, one after the other
+    const size_t nrest = h.rest.size();
+    const size_t rest_stride = align_up(sizeof(float) * nrest);
+    const size_t rowk_stride = align_up(sizeof(CellRowK<float>) * nt);
     const struct { size_t off; const void* src; size_t bytes; } upk[] = {
+        {L.rest_f, rest_f.data(), nrest * sizeof(float)},
+        {L.rest_f + rest_stride, rest_f.data() + nrest, nrest * sizeof(float)},
+        {L.rest_f + 2 * rest_stride, rest_f.data() + 2 * nrest, nrest * sizeof(float)},
         {L.rowk, rkd.data(), rkd.size() * sizeof(rkd[0])},
-        {L.rowk_f, rkf.data(), rkf.size() * sizeof(rkf[0])},
+        {L.rowk_f, rkf.data(), nt * sizeof(rkf[0])},
+        {L.rowk_f + rowk_stride, rkf.data() + nt, nt * sizeof(rkf[0])},
+        {L.rowk_f + 2 * rowk_stride, rkf.data() + 2 * nt, nt * sizeof(rkf[0])},
         {L.facek, fkd.data(), fkd.size() * sizeof(fkd[0])},
         {L.facek_f, fkf.data(), fkf.size() * sizeof(fkf[0])}};
     for (const auto& u : upk)
