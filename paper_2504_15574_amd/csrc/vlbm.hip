@@ -370,8 +370,13 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
 // fluxes U1/U2/U3 (order read per run) with the interface factor.  A launch
 // covers runs of one variant.
 enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
+// Minimum waves per SIMD the register allocation must allow: 7 for the default
+// float kernel (72 VGPRs; measured +0.7 % over 6 waves at 74), 6 for the other
+// float variants, 4 for FP64.
+template <class T, int VAR>
+constexpr int stage_min_waves() { return sizeof(T) == 8 ? 4 : (VAR == VAR_WENO ? 7 : 6); }
 template <class St, bool BATCH, class Tl, int VAR, int NQ>
-__global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) void stage_kernel(StageArgs A) {
     constexpr bool GEN = VAR != VAR_WENO, UPW = VAR == VAR_UPWIND;
     constexpr int NK = NQ * NQ;
     constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR;
@@ -647,8 +652,53 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         const T a = vouter(kt) ? ato : ati, b = vouter(kp) ? apo : api;
         return (vsgn(kt) < 0 ? -a : a) + (vsgn(kp) < 0 ? -b : b);
     };
-    // rho (1 + P) - rho0 = drho + rho P for the population and its mirror
-    T tk[NK];
+    const T ca = uni<T>(D, U_A), cb = uni<T>(D, U_B);
+    const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
+    const rsrc_t rout = make_rsrc(D.out, NK * planeB);
+    const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
+    // float kernels.  A reduced-precision store adds, every stage, nearly the
+    // same increment to nearly the same value: rounding to nearest then makes
+    // nearly the same error every step, and those errors add up coherently
+    // (linear instead of square-root growth in the number of steps).  Two
+    // measures keep the error at rounding level:
+    //  - the register sums hold only the increment dt L (the stage input g of
+    //    the cell is kept aside in registers), so the arithmetic rounds at the
+    //    scale of the increment, and g + increment is rounded once;
+    //  - that one rounding is dithered: a value uniform in [-1/2, 1/2) ulp is
+    //    added before rounding to nearest, which makes the rounding unbiased
+    //    (stochastic rounding).  The dither of population k is h + k c mod
+    //    2^32 (c = 2^32 (sqrt5 - 1)/2, a Weyl step), where h is a 32-bit hash
+    //    (the "lowbias32" xorshift-multiply mixer) of the cell index, the
+    //    step counter and the stage.  A dither shared by all cells would
+    //    resonate with cells whose per-step increment matches its own step.
+    //    It depends on the step count only, so batched, single and
+    //    graph-replayed steps give identical bits.
+    uint32_t hsh = 0;
+    if constexpr (sizeof(T) != 8) {
+        hsh = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) ^ (*D.ctr * 0x9E3779B9u + D.seq * 0x85EBCA6Bu);
+        hsh ^= hsh >> 16; hsh *= 0x7feb352du;
+        hsh ^= hsh >> 15; hsh *= 0x846ca68bu;
+        hsh ^= hsh >> 16;
+    }
+    // store population k, whose equilibrium deviation is w_k (drho + rho P)
+    auto finish = [&](int k, T t) {
+        if constexpr (sizeof(T) == 8) {
+            // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
+            const T y = fma(dti * C.wk[k], t, acc[k]);
+            T o = cb * y;
+            if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+            St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
+        } else {
+            const T g = gk[k];
+            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
+            // kernels' row factors, rest table and dt/tau come multiplied by b
+            T d = fma(dti, fma(C.wk[k], t, -g), acc[k]);
+            if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
+            const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
+            St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
+        }
+    };
+    // drho + rho P for each population and its mirror, stored pair by pair
 #pragma unroll
     for (int k = 0; 2 * k < NK - 1; ++k) {
         const T xi = xi_of(k);
@@ -658,57 +708,10 @@ __global__ __launch_bounds__(NTHR) void stage_kernel(StageArgs A) {
         if constexpr (NQ == 4) od = fma(xi, fma(x2, T(1.0 / 6.0), cu), xi);
         else od = fma(xi, C.eq_e1, xi);
         const T ro = rho * od;
-        tk[k] = base + ro;
-        tk[NK - 1 - k] = base - ro;
+        finish(k, base + ro);
+        finish(NK - 1 - k, base - ro);
     }
-    if constexpr (NK & 1) tk[NK / 2] = fma(rho, ev0, drho);     // xi = 0
-    const T ca = uni<T>(D, U_A), cb = uni<T>(D, U_B);
-    const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
-    const rsrc_t rout = make_rsrc(D.out, NK * planeB);
-    const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
-    if constexpr (sizeof(T) == 8) {
-        // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const T y = fma(dti * C.wk[k], tk[k], acc[k]);
-            T o = cb * y;
-            if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
-            St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
-        }
-    } else {
-        // float kernels.  A reduced-precision store adds, every stage, nearly the
-        // same increment to nearly the same value: rounding to nearest then makes
-        // nearly the same error every step, and those errors add up coherently
-        // (linear instead of square-root growth in the number of steps).  Two
-        // measures keep the error at rounding level:
-        //  - the register sums hold only the increment dt L (the stage input g of
-        //    the cell is kept aside in registers), so the arithmetic rounds at the
-        //    scale of the increment, and g + increment is rounded once;
-        //  - that one rounding is dithered: a value uniform in [-1/2, 1/2) ulp is
-        //    added before rounding to nearest, which makes the rounding unbiased
-        //    (stochastic rounding).  The dither of population k is h + k c mod
-        //    2^32 (c = 2^32 (sqrt5 - 1)/2, a Weyl step), where h is a 32-bit hash
-        //    (the "lowbias32" xorshift-multiply mixer) of the cell index, the
-        //    step counter and the stage.  A dither shared by all cells would
-        //    resonate with cells whose per-step increment matches its own step.
-        //    It depends on the step count only, so batched, single and
-        //    graph-replayed steps give identical bits.
-        uint32_t hsh = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) ^
-                       (*D.ctr * 0x9E3779B9u + D.seq * 0x85EBCA6Bu);
-        hsh ^= hsh >> 16; hsh *= 0x7feb352du;
-        hsh ^= hsh >> 15; hsh *= 0x846ca68bu;
-        hsh ^= hsh >> 16;
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const T g = gk[k];
-            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
-            // kernels' row factors, rest table and dt/tau come multiplied by b
-            T d = fma(dti, fma(C.wk[k], tk[k], -g), acc[k]);
-            if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
-            const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
-            St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
-        }
-    }
+    if constexpr (NK & 1) finish(NK / 2, fma(rho, ev0, drho));     // xi = 0
 }
 
 // ---------------------------------------------------------------------------
