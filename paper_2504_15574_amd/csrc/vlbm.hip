@@ -608,10 +608,13 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
                 acc[b * NQ + kp] += C.fa[(kp * NQ + b) * NQ + kt] * tg;
                 acc[kt * NQ + b] += C.fb[(kt * NQ + b) * NQ + kp] * tg;
             }
-            if constexpr (sizeof(T) != 8) gk[k] = gc;
-            drho += gc;
-            jt += C.v[kt] * gc;
-            jp += C.v[kp] * gc;
+            if constexpr (sizeof(T) != 8) {
+                gk[k] = gc;                          // moments from these at the end
+            } else {
+                drho += gc;
+                jt += C.v[kt] * gc;
+                jp += C.v[kp] * gc;
+            }
         }
         if (k + 2 < NK) lstore(k + 2, (k + 2) % 3, nx0, nx1);
         // keep this population's register arithmetic in place: deferring it past
@@ -620,11 +623,11 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
                          "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]), "+v"(acc[9]),
                          "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]), "+v"(acc[14]),
-                         "+v"(acc[15]), "+v"(drho), "+v"(jt), "+v"(jp));
+                         "+v"(acc[15]));
         else
             asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
-                         "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]), "+v"(drho),
-                         "+v"(jt), "+v"(jp));
+                         "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]));
+        if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(drho), "+v"(jt), "+v"(jp));
     }
 
     if (!valid) return;
@@ -637,6 +640,30 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     // population NK-1-k has -xi and the same weight, so each pair shares the
     // even part of P and flips the sign of its odd part, which is formed as
     // xi + xi (...) so that no rounding scales the linear term.
+    if constexpr (sizeof(T) != 8) {
+        // moments of the kept inputs from the row sums S_kt and column sums P_kp:
+        // the nodes are -v_o, -v_i, v_i, v_o (Q = 3: -v_o, 0, v_o)
+        T S[NQ], P[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            S[i] = gk[i * NQ];
+            P[i] = gk[i];
+#pragma unroll
+            for (int j = 1; j < NQ; ++j) {
+                S[i] += gk[i * NQ + j];
+                P[i] += gk[j * NQ + i];
+            }
+        }
+        drho = S[0];
+#pragma unroll
+        for (int i = 1; i < NQ; ++i) drho += S[i];
+        jt = C.v[NQ - 1] * (S[NQ - 1] - S[0]);
+        jp = C.v[NQ - 1] * (P[NQ - 1] - P[0]);
+        if constexpr (NQ == 4) {
+            jt = fma(C.v[2], S[2] - S[1], jt);
+            jp = fma(C.v[2], P[2] - P[1], jp);
+        }
+    }
     const T rho0 = uni<T>(D, U_RHO0);
     const T rho = rho0 + drho;
     const T irho = rcp_nr(rho);
