@@ -370,11 +370,12 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
 // fluxes U1/U2/U3 (order read per run) with the interface factor.  A launch
 // covers runs of one variant.
 enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
-// Minimum waves per SIMD the register allocation must allow: 7 for the default
-// float kernel (72 VGPRs; measured +0.7 % over 6 waves at 74), 6 for the other
-// float variants, 4 for FP64.
+// Minimum waves per SIMD the register allocation must allow: 7 for the float
+// kernels (at most 72 VGPRs; the general WENO-5 variant keeps two values in
+// scratch across the population loop and still gains 3.7 % over 6 waves), 4 for
+// FP64 (5 waves would spill inside the loop: 38 % slower).
 template <class T, int VAR>
-constexpr int stage_min_waves() { return sizeof(T) == 8 ? 4 : (VAR == VAR_WENO ? 7 : 6); }
+constexpr int stage_min_waves() { return sizeof(T) == 8 ? 4 : 7; }
 template <class St, bool BATCH, class Tl, int VAR, int NQ>
 __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) void stage_kernel(StageArgs A) {
     constexpr bool GEN = VAR != VAR_WENO, UPW = VAR == VAR_UPWIND;
