@@ -424,6 +424,9 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     uint32_t la[2], lm[2];
     int ldst[2];
     T lsin[2];
+    // a tile whose halo lies inside the grid (no pole rows, no phi wrap): the
+    // descriptors need no folding (uniform per workgroup)
+    const bool inner = s0 >= NGH && s0 + TS + NGH <= nt && q0 >= NGH && q0 + TQ + NGH <= np;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         int idx = tid + NTHR * j;
@@ -438,20 +441,22 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             r = e2 / NGH + NGH;
             c = (e < TS * NGH) ? e2 % NGH : TQ + NGH + e2 % NGH;
         }
-        // column q0 - 3 + c lies in [-3, np + TQ + 2]: one fold suffices when np >= TQ + 3
-        int ss = s0 - NGH + r;
-        int qq = np >= TQ + NGH ? wrap1(q0 - NGH + c, np) : wrap(q0 - NGH + c, np);
+        int ss = s0 - NGH + r, qq = q0 - NGH + c;
         bool mir = false;
-        if (ss < 0) {                   // north pole: row -m <- row m-1 at phi + pi, v -> -v
-            ss = -1 - ss;
-            mir = true;
-            qq = wrap1(qq + half, np);
-        } else if (ss >= nt) {          // south pole: row nt-1+m <- row nt-m
-            ss = 2 * nt - 1 - ss;
-            mir = true;
-            qq = wrap1(qq + half, np);
+        if (!inner) {
+            // column q0 - 3 + c lies in [-3, np + TQ + 2]: one fold suffices when np >= TQ + 3
+            qq = np >= TQ + NGH ? wrap1(qq, np) : wrap(qq, np);
+            if (ss < 0) {                   // north pole: row -m <- row m-1 at phi + pi, v -> -v
+                ss = -1 - ss;
+                mir = true;
+                qq = wrap1(qq + half, np);
+            } else if (ss >= nt) {          // south pole: row nt-1+m <- row nt-m
+                ss = 2 * nt - 1 - ss;
+                mir = true;
+                qq = wrap1(qq + half, np);
+            }
+            ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
         }
-        ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
         ldst[j] = used ? SL::at(r, c) : SL::SIZE;
         la[j] = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
         lm[j] = mir ? ~0u : 0u;
