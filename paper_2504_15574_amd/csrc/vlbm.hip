@@ -386,8 +386,11 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     constexpr int B = St::B;
     using SL = SlotLayout<Tl, (int)sizeof(T)>;
     constexpr int PAD = 8;                     // destination of the unused load slots
-    __shared__ T tile[3][SL::SIZE + PAD];      // g of one population, cross-shaped halo
-    __shared__ T tileh[3][SL::SIZE + PAD];     // theta flux function v sin(theta_j) g_j
+    // the three ring slots are interleaved element by element (element i of
+    // slot b at 3 i + b): a thread's stencil reads in any slot then sit at small
+    // constant offsets from one base address, so no per-slot address arithmetic
+    __shared__ T tile[3 * (SL::SIZE + PAD)];   // g of one population, cross-shaped halo
+    __shared__ T tileh[3 * (SL::SIZE + PAD)];  // sin(theta_j) g_j: theta flux function without its speed
     __shared__ T fth[2][NFT];
     __shared__ T fph[2][NFP + 1];              // faces with phi index < TQ row-major, then the TS right faces
 
@@ -471,11 +474,11 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     auto vsgn = [](int i) { return 2 * i + 1 < NQ ? -1 : (2 * i + 1 > NQ ? 1 : 0); };
     auto vouter = [](int i) { return i == 0 || i == NQ - 1; };
     auto lstore = [&](int k, int buf, T v0, T v1) {
-        tile[buf][ldst[0]] = v0;
-        tile[buf][ldst[1]] = v1;
+        tile[3 * ldst[0] + buf] = v0;
+        tile[3 * ldst[1] + buf] = v1;
         if (vsgn(k / NQ) != 0) {              // theta flux function without its speed
-            tileh[buf][ldst[0]] = lsin[0] * v0;
-            tileh[buf][ldst[1]] = lsin[1] * v1;
+            tileh[3 * ldst[0] + buf] = lsin[0] * v0;
+            tileh[3 * ldst[1] + buf] = lsin[1] * v1;
         }
     };
 
@@ -550,8 +553,8 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
                 const int a = (m & 1 ? tbase1 : tbase0) + (m >> 1) * SL::RS2;
-                g[m] = tile[tb][a];
-                h[m] = tileh[tb][a];
+                g[m] = tile[3 * a + tb];
+                h[m] = tileh[3 * a + tb];
             }
             gself = g[3];                                // this thread's cell (row ti, column tc)
             T F;
@@ -569,13 +572,13 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             fth[fb][tid] = F;
             Ftself = F;                                  // top face of this thread's cell
         } else {
-            gself = tile[tb][tbase1 + SL::RS2];          // LDS row ti+3
+            gself = tile[3 * (tbase1 + SL::RS2) + tb];   // LDS row ti+3
         }
         // phi flux of g (the speed multiplies the difference)
         if (sp != 0) {
             T g[6];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) g[m] = tile[tb][pbase + m];
+            for (int m = 0; m < 6; ++m) g[m] = tile[3 * (pbase + m) + tb];
             T F;
             if constexpr (!UPW) {
                 if (sp > 0)
