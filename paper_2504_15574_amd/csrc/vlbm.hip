@@ -353,7 +353,12 @@ struct SlotLayout {
     static constexpr bool SPLIT = BYTES == 4 && Tl::TQ == 16;
     static constexpr int OB = SPLIT ? ((Tl::LR + 1) / 2) * 32 + 16 : Tl::LC;   // row 1
     static constexpr int RS2 = SPLIT ? 32 : 2 * Tl::LC;                         // row r -> r + 2
-    static constexpr int SIZE = SPLIT ? OB + (Tl::LR / 2) * 32 : Tl::LT;
+    // last even row's end: the gap up to OB takes the unused load slots
+    static constexpr int EVEN_END = ((Tl::LR - 1) >> 1) * 32 + Tl::LC;
+    static_assert(!SPLIT || EVEN_END < OB, "slot layout");
+    // elements per slot (past the last odd row) and where unused load slots write
+    static constexpr int SIZE = SPLIT ? OB + ((Tl::LR - 2) >> 1) * 32 + Tl::LC : Tl::LT + 8;
+    static constexpr int DUMMY = SPLIT ? EVEN_END : Tl::LT;
     __device__ static int at(int r, int c) { return (r & 1) * OB + (r >> 1) * RS2 + c; }
 };
 using Tile15x16 = TileShape<15, 16>;
@@ -385,12 +390,11 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     using T = typename St::T;
     constexpr int B = St::B;
     using SL = SlotLayout<Tl, (int)sizeof(T)>;
-    constexpr int PAD = 8;                     // destination of the unused load slots
     // the three ring slots are interleaved element by element (element i of
     // slot b at 3 i + b): a thread's stencil reads in any slot then sit at small
     // constant offsets from one base address, so no per-slot address arithmetic
-    __shared__ T tile[3 * (SL::SIZE + PAD)];   // g of one population, cross-shaped halo
-    __shared__ T tileh[3 * (SL::SIZE + PAD)];  // sin(theta_j) g_j: theta flux function without its speed
+    __shared__ T tile[3 * SL::SIZE];           // g of one population, cross-shaped halo
+    __shared__ T tileh[3 * SL::SIZE];          // sin(theta_j) g_j: theta flux function without its speed
     __shared__ T fth[2][NFT];
     __shared__ T fph[2][NFP + 1];              // faces with phi index < TQ row-major, then the TS right faces
 
@@ -460,7 +464,7 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             }
             ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
         }
-        ldst[j] = used ? SL::at(r, c) : SL::SIZE;
+        ldst[j] = used ? SL::at(r, c) : SL::DUMMY;
         la[j] = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
         lm[j] = mir ? ~0u : 0u;
         const int js = s0 + r;                        // sin table index of row s0 - 3 + r
