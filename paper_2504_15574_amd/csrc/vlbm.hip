@@ -88,6 +88,8 @@ struct ConstsT {
     // FP32 v_k w_k (FP64 node and weight) over the FP32 node, so that the speed
     // factor times it reproduces the FP64 product the rest-state tables use
     T wr[NKMAX];
+    T K[NKMAX], Kt[NKMAX];   // the force kernels K^H, K~^H (row-major, stride Q)
+    T nv2[NQMAX];            // -v^2 per node
     // equilibrium coefficients that make its mass and momentum exact on the
     // rule's own moments S2 = sum w v^2, S4 = sum w v^4, S22 = sum w vt^2 vp^2
     T eq_e1;    // 1/S2 - 1 (extra weight of the linear term)
@@ -526,6 +528,15 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
         gk[k] = T(0);
     }
     T drho = T(0), jt = T(0), jp = T(0);
+    // the loop's uniform constants, read once into scalar registers so that the
+    // population loop issues no scalar loads (whose waits would also wait for
+    // the outstanding LDS reads); the float force uses the kernels K^H, K~^H
+    // (32 values) instead of the 128 premultiplied fa, fb
+    T CK[NK], CKt[NK], Cwr[NK], Cv[NQ], Cnv2[NQ];
+#pragma unroll
+    for (int i = 0; i < NK; ++i) { CK[i] = C.K[i]; CKt[i] = C.Kt[i]; Cwr[i] = C.wr[i]; }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) { Cv[i] = C.v[i]; Cnv2[i] = C.nv2[i]; }
 
     // Ring of three LDS slots: population p lives in slot p % 3.  Its global
     // loads are issued at the start of iteration p - 2 and it is written to LDS
@@ -565,10 +576,10 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             if constexpr (!UPW) {
                 if (st > 0)
                     F = weno5x6<T, true>(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4],
-                                         epsk, C.wr[k], fk.cp1, fk.cp3);
+                                         epsk, Cwr[k], fk.cp1, fk.cp3);
                 else
                     F = weno5x6<T, true>(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1],
-                                         epsk, C.wr[k], fk.cm1, fk.cm3);
+                                         epsk, Cwr[k], fk.cm1, fk.cm3);
             } else {
                 F = st > 0 ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
             }
@@ -616,10 +627,20 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             }
             acc[k] = a;
             const T tg = rk.dtcot * gc;
+            if constexpr (sizeof(T) == 8) {
 #pragma unroll
-            for (int b = 0; b < NQ; ++b) {
-                acc[b * NQ + kp] += C.fa[(kp * NQ + b) * NQ + kt] * tg;
-                acc[kt * NQ + b] += C.fb[(kt * NQ + b) * NQ + kp] * tg;
+                for (int b = 0; b < NQ; ++b) {
+                    acc[b * NQ + kp] += C.fa[(kp * NQ + b) * NQ + kt] * tg;
+                    acc[kt * NQ + b] += C.fb[(kt * NQ + b) * NQ + kp] * tg;
+                }
+            } else {
+                // fa = -v_kp^2 K[b][kt], fb = v_kt K~[b][kp] applied as two scalings of tg
+                const T ta = Cnv2[kp] * tg, tb = Cv[kt] * tg;
+#pragma unroll
+                for (int b = 0; b < NQ; ++b) {
+                    acc[b * NQ + kp] = fma(CK[b * NQ + kt], ta, acc[b * NQ + kp]);
+                    acc[kt * NQ + b] = fma(CKt[b * NQ + kp], tb, acc[kt * NQ + b]);
+                }
             }
             if constexpr (sizeof(T) != 8) {
                 gk[k] = gc;                          // moments from these at the end
@@ -1642,6 +1663,14 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     for (int i = 0; i < q * q * q; ++i) {
         x->cd.fa[i] = x->c.fa[i]; x->cf.fa[i] = (float)x->c.fa[i];
         x->cd.fb[i] = x->c.fb[i]; x->cf.fb[i] = (float)x->c.fb[i];
+    }
+    for (int i = 0; i < q * q; ++i) {
+        x->cd.K[i] = x->c.K[i]; x->cf.K[i] = (float)x->c.K[i];
+        x->cd.Kt[i] = x->c.Kt[i]; x->cf.Kt[i] = (float)x->c.Kt[i];
+    }
+    for (int i = 0; i < q; ++i) {
+        x->cd.nv2[i] = -x->c.v[i] * x->c.v[i];
+        x->cf.nv2[i] = (float)(-x->c.v[i] * x->c.v[i]);
     }
     HostRows h;
     build_rows(h, *p, x->c);
