@@ -248,9 +248,10 @@ struct StF16 {
 // with G2 = 6 F2, A = 3 (F1 - F2), B = 6 (F3 - F2); multiplying numerator and
 // denominator of the weights by q1 q2 q3 needs a single reciprocal.  The
 // indicators are carried as a^2 + (3/13) b^2 (12/13 of sigma, with eps scaled
-// to match), which leaves the normalised weights unchanged.  REST: vw c1 and
-// vw c3 add the rest state's candidate differences, which share the weights
-// (theta direction; c1, c3 arrive scaled by 3 and 6).
+// to match), which leaves the normalised weights unchanged.  REST: wr c1 and
+// wr c3 add the rest state's candidate differences, which share the weights
+// (theta direction; c1, c3 arrive scaled by 3 and 6; wr is the rest weight per
+// unit speed, since the caller multiplies the flux difference by the speed).
 template <class T> __device__ __forceinline__ T rcp_(T x);
 template <> __device__ __forceinline__ float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double rcp_<double>(double x) {
@@ -267,13 +268,13 @@ template <class T> __device__ __forceinline__ T rcp_nr(T x) {
 
 template <class T, bool REST>
 __device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g2, T g3, T g4,
-                                     T epsk, T vw, T c1, T c3) {
+                                     T epsk, T wr, T c1, T c3) {
     const T G2 = fma(T(5), h2, fma(T(2), h3, -h1));            // 6 F2
     T A = fma(T(3), h2 - h1, h0 - h3);                          // 3 (F1 - F2)
     T B = fma(T(3), h3 - h2, h1 - h4);                          // 6 (F3 - F2)
     if constexpr (REST) {
-        A = fma(vw, c1, A);
-        B = fma(vw, c3, B);
+        A = fma(wr, c1, A);
+        B = fma(wr, c3, B);
     }
     const T D0 = g1 - g0, D1 = g2 - g1, D2 = g3 - g2, D3 = g4 - g3;
     const T a1 = D1 - D0, a2 = D2 - D1, a3 = D3 - D2;
@@ -322,9 +323,10 @@ __device__ __forceinline__ int wrap1(int q, int np) {
 // gathered from column q + np/2 and population 15 - k, phi periodic) sits in a
 // triple-buffered LDS slot, so the global loads of population k+2 overlap the
 // fluxes of population k and one barrier per population suffices.  The 240
-// cell threads accumulate dt*L for all 16 populations in registers: advection,
-// the rest-state table, -g/tau and the rank-1 updates of the inertial force;
-// the equilibrium is added at the end from the accumulated moments.
+// cell threads accumulate dt*L for all 16 populations in registers, starting
+// from the rest-state table: advection and the rank-1 updates of the inertial
+// force (FP64 also -g/tau); the equilibrium is added at the end from the
+// moments (FP64: running sums; float: sums of the 16 inputs kept in registers).
 // Workgroups are numbered so that those sharing an XCD (dispatched round-robin
 // over the 8 XCDs) take a contiguous range of tiles, keeping halo rows and the
 // 64-byte halves of shared cache lines inside one L2.
