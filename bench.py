@@ -189,7 +189,7 @@ def run_ensemble(steps):
     mlups = lambda ms: round(cells * steps / (ms * 1e-3) / 1e6, 1)
     return {"workload": "64 shock runs: 32 x 128x256 + 32 x 256x512, D2Q16, f32 deviation store",
             "steps": steps, "cells": cells, "grouping": ens.grouping,
-            "tile": f"{ens.tile[0]}x{ens.tile[1]}",
+            "tile": ens.tile_name(),
             "autotune_ms_per_step": {k: round(v, 4) for k, v in tune.items()},
             "mlups_one_run_per_launch": mlups(one), "mlups_batched": mlups(bat),
             "mlups_batched_graph": mlups(gr), "finite": finite}

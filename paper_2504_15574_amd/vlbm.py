@@ -330,9 +330,11 @@ class Ensemble:
     (``"all"``: one launch per RK stage for everything, 64 runs per launch;
     ``"by_size"``: one launch per distinct grid; ``"single"``: one launch per
     run) and ``tile`` is the stage kernel's tile shape (15 x 16 or 7 x 32,
-    rows x columns).  ``autotune`` times the combinations and keeps the
-    fastest.  ``capture``/``replay`` record and replay a fixed number of steps
-    as HIP graphs (one per launch group)."""
+    rows x columns): one shape for every run, or, with ``"by_size"``, a dict
+    {(n_theta, n_phi): shape} that lets each grid size use its own.
+    ``autotune`` times the combinations and keeps the fastest.
+    ``capture``/``replay`` record and replay a fixed number of steps as HIP
+    graphs (one per launch group)."""
 
     GROUPINGS = ("all", "by_size", "single")
     TILES = ((15, 16), (7, 32))
@@ -342,20 +344,33 @@ class Ensemble:
         self.graphs = []
         self.graph_steps = 0
         self.tile = None
+        self.grouping = None
         self.configure(grouping, tile)
+
+    @staticmethod
+    def _size(s):
+        return (s.n_theta, s.n_phi)
 
     def configure(self, grouping=None, tile=None):
         grouping = self.grouping if grouping is None else grouping
-        tile = self.tile if tile is None else tuple(tile)
+        tile = self.tile if tile is None else tile
         if grouping not in self.GROUPINGS:
             raise ValueError(grouping)
-        if tile not in self.TILES:
-            raise ValueError(tile)
+        if isinstance(tile, dict):
+            if grouping != "by_size":
+                raise ValueError("a tile shape per grid size needs grouping 'by_size'")
+            tile = {tuple(k): tuple(v) for k, v in tile.items()}
+            if set(tile) != {self._size(s) for s in self.solvers} or \
+                    any(v not in self.TILES for v in tile.values()):
+                raise ValueError(tile)
+        else:
+            tile = tuple(tile)
+            if tile not in self.TILES:
+                raise ValueError(tile)
         self.release()
-        if tile != self.tile:
-            for s in self.solvers:
-                vlbm_set_tile_shape(s.ctx, *tile)
-            self.tile = tile
+        for s in self.solvers:
+            vlbm_set_tile_shape(s.ctx, *(tile[self._size(s)] if isinstance(tile, dict) else tile))
+        self.tile = tile
         self.grouping = grouping
         if grouping == "all":
             groups = [self.solvers]
@@ -364,9 +379,22 @@ class Ensemble:
         else:
             by = {}
             for s in self.solvers:
-                by.setdefault((s.n_theta, s.n_phi), []).append(s)
+                by.setdefault(self._size(s), []).append(s)
             groups = list(by.values())
         self.groups = [[s.ctx for s in g] for g in groups]
+        self._group_sizes = [self._size(g[0]) for g in groups]
+
+    def _step_size(self, ctxs, size, n):
+        vlbm_step_batch(ctxs, n)
+        for s in self.solvers:
+            if self._size(s) == size:
+                s.t += n * s.dt
+
+    def tile_name(self):
+        """The tile choice as text: "15x16", or "128x256:7x32,256x512:15x16"."""
+        if isinstance(self.tile, dict):
+            return ",".join(f"{k[0]}x{k[1]}:{v[0]}x{v[1]}" for k, v in sorted(self.tile.items()))
+        return f"{self.tile[0]}x{self.tile[1]}"
 
     def set_grouping(self, grouping):
         self.configure(grouping=grouping)
@@ -395,25 +423,49 @@ class Ensemble:
 
     def autotune(self, steps=10, groupings=GROUPINGS, tiles=TILES):
         """Time ``steps`` eager steps per (grouping, tile) combination (this
-        advances the runs) and keep the fastest; returns
-        {"grouping/rowsxcols": ms per step}."""
+        advances the runs) and keep the fastest; with "by_size" and several
+        grid sizes, also the combination of each size's fastest tile shape on
+        its own launches.  Returns {"grouping/tile": ms per step}."""
         import torch
+
+        def timed(fn):
+            fn(1)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(self.solvers[0].stream)
+            fn(steps)
+            e1.record(self.solvers[0].stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+
         times = {}
         for t in tiles:
             for c in groupings:
                 self.configure(c, t)
-                self.step(1)
-                torch.cuda.synchronize()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(self.solvers[0].stream)
-                self.step(steps)
-                e1.record(self.solvers[0].stream)
-                torch.cuda.synchronize()
-                times[(c, t)] = e0.elapsed_time(e1) / steps
-        best = min(times, key=times.get)
-        self.configure(*best)
-        return {f"{c}/{t[0]}x{t[1]}": v for (c, t), v in times.items()}
+                times[(c, t)] = timed(self.step)
+        sizes = {self._size(s) for s in self.solvers}
+        if "by_size" in groupings and len(sizes) > 1 and len(tiles) > 1:
+            per = {}
+            for t in tiles:
+                self.configure("by_size", t)
+                for g, sz in zip(self.groups, self._group_sizes):
+                    per[(sz, t)] = timed(lambda n, g=g, sz=sz: self._step_size(g, sz, n))
+            mix = {sz: min(tiles, key=lambda t: per[(sz, t)]) for sz in sizes}
+            if len(set(mix.values())) > 1:
+                self.configure("by_size", mix)
+                times[("by_size", tuple(sorted(mix.items())))] = timed(self.step)
+        c, t = min(times, key=times.get)
+        per_size = isinstance(t[0], tuple)
+        self.configure(c, dict(t) if per_size else t)
+        out = {}
+        for (c, t), v in times.items():
+            if isinstance(t[0], tuple):
+                key = ",".join(f"{k[0]}x{k[1]}:{w[0]}x{w[1]}" for k, w in t)
+            else:
+                key = f"{t[0]}x{t[1]}"
+            out[f"{c}/{key}"] = v
+        return out
 
     def __del__(self):
         try:

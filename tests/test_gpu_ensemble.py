@@ -164,6 +164,28 @@ def test_tile_shape_errors_and_autotuner():
         vlbm_step_batch([a.ctx, b.ctx], 1)          # mixed tile shapes
     ens = Ensemble([a, b])
     times = ens.autotune(steps=2)
-    assert len(times) == 6 and ens.tile in Ensemble.TILES
+    assert len(times) == 6 and ens.tile in Ensemble.TILES     # one grid size: no per-size choice
+    with pytest.raises(ValueError):
+        ens.configure("all", {(16, 32): (7, 32)})           # per-size tiles need "by_size"
     a.close()
     b.close()
+
+
+def test_autotuner_per_size_tiles_keep_the_bits():
+    # Two grid sizes: the tuner also tries each size's own fastest tile shape;
+    # whatever it picks, the runs match the same runs stepped one by one.
+    from paper_2504_15574_amd import Ensemble
+    sizes = [(16, 32), (30, 64), (16, 32), (30, 64)]
+    runs = _runs("f32", sizes, seed=17)
+    ref = _runs("f32", sizes, seed=17)
+    ens = Ensemble(runs)
+    times = ens.autotune(steps=2)
+    assert len(times) in (6, 7) and all(v > 0 for v in times.values())
+    ens.configure("by_size", {(16, 32): (7, 32), (30, 64): (15, 16)})
+    assert ens.tile_name() == "16x32:7x32,30x64:15x16"
+    ens.step(3)
+    for s, r in zip(runs, ref):                           # the same number of steps one by one
+        r.step(round((s.t - r.t) / r.dt))
+        assert np.array_equal(s.populations(), r.populations())
+    for s in runs + ref:
+        s.close()
