@@ -79,6 +79,10 @@ def test_init_matches_oracle_equilibrium():
     (22, 192, 2, True),      # twelve phi tiles
     (37, 1, 3, False),       # axisymmetric, odd n_theta
     (8, 130, 4, False),      # one partial tile row; every row is a pole row
+    (3, 2, 5, False),        # the smallest grid: every ghost row maps back into the grid
+    (5, 18, 6, False),       # n_phi below TQ + 3: columns wrap with the integer modulo
+    (6, 20, 7, False),       # n_phi = 20: the one-fold column wrap
+    (48, 64, 8, True),       # interior tiles (halo inside the grid) beside boundary tiles
 ])
 def test_f64_parity_random_states(nt, nph, seed, smooth):
     st = W.random_state(nt, nph, seed=seed, du=0.05, dT=0.05, smooth=smooth)
