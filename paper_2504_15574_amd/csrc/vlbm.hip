@@ -63,10 +63,6 @@ struct Consts {
     double Kt[NKMAX];         // K~^H
     double scale[NKMAX];      // FP16 storage scale 2^e_k (1 for the other formats)
     double iscale[NKMAX];     // 1 / scale
-    // rank-1 form of the inertial force: population (kt, kp) adds
-    //   fa[kp][a][kt] * cot g  to G_(a, kp)   and   fb[kt][b][kp] * cot g  to G_(kt, b)
-    double fa[NQMAX * NKMAX];   // -v_kp^2 K[a][kt]
-    double fb[NQMAX * NKMAX];   //  v_kt Kt[b][kp]
 };
 
 // per-row tables in the workspace (FP64)
@@ -83,7 +79,7 @@ struct Rows {
 // the constants the stage kernel uses, in its arithmetic type
 template <class T>
 struct ConstsT {
-    T v[NQMAX], wk[NKMAX], fa[NQMAX * NKMAX], fb[NQMAX * NKMAX], scale[NKMAX], iscale[NKMAX];
+    T v[NQMAX], wk[NKMAX], scale[NKMAX], iscale[NKMAX];
     // weight of the rest state's theta flux per unit node speed: w_k in FP64; in
     // FP32 v_k w_k (FP64 node and weight) over the FP32 node, so that the speed
     // factor times it reproduces the FP64 product the rest-state tables use
@@ -361,7 +357,7 @@ struct SlotLayout {
     static constexpr int EVEN_END = ((Tl::LR - 1) >> 1) * 32 + Tl::LC;
     static_assert(!SPLIT || EVEN_END < OB, "slot layout");
     // elements per slot (past the last odd row) and where unused load slots write
-    static constexpr int SIZE = SPLIT ? OB + ((Tl::LR - 2) >> 1) * 32 + Tl::LC : Tl::LT + 8;
+    static constexpr int SIZE = SPLIT ? OB + ((Tl::LR - 2) >> 1) * 32 + Tl::LC : Tl::LT + (BYTES == 8 ? 1 : 8);
     static constexpr int DUMMY = SPLIT ? EVEN_END : Tl::LT;
     __device__ static int at(int r, int c) { return (r & 1) * OB + (r >> 1) * RS2 + c; }
 };
@@ -381,10 +377,11 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
 enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
 // Minimum waves per SIMD the register allocation must allow: 7 for the float
 // kernels (at most 72 VGPRs; the general WENO-5 variant keeps two values in
-// scratch across the population loop and still gains 3.7 % over 6 waves), 4 for
-// FP64 (5 waves would spill inside the loop: 38 % slower).
+// scratch across the population loop and still gains 3.7 % over 6 waves), 5 for
+// FP64 (at most 96 VGPRs, which needs its row factors in LDS; its LDS use,
+// 32 KB per workgroup, also allows no more).
 template <class T, int VAR>
-constexpr int stage_min_waves() { return sizeof(T) == 8 ? 4 : 7; }
+constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
 template <class St, bool BATCH, class Tl, int VAR, int NQ>
 __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) void stage_kernel(StageArgs A) {
     constexpr bool GEN = VAR != VAR_WENO, UPW = VAR == VAR_UPWIND;
@@ -495,7 +492,6 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     const int tbase0 = SL::at(ti, tc + NGH);             // LDS rows ti, ti+2, ti+4
     const int tbase1 = SL::at(ti + 1, tc + NGH);         // LDS rows ti+1, ti+3, ti+5
     const int ig = s0 + ti < nt ? s0 + ti : nt;          // global interface index
-    const FaceRowK<T> fk = static_cast<const FaceRowK<T>*>(D.facek)[ig];
     const int scheme = UPW ? D.scheme : (int)VLBM_ADV_WENO5;
     // ---- phi interface of this thread: the left face of its cell for the 240
     // cell threads, the right faces of column 15 for threads 240..254
@@ -513,7 +509,43 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     const bool valid = cell && cs < nt && cq < np;
     const int csc = cs < nt ? cs : nt - 1;
     const int rslot = cc + 1 < TQ ? cr * TQ + cc + 1 : TS * TQ + cr;   // right face of the cell
-    const CellRowK<T> rk = static_cast<const CellRowK<T>*>(D.rowk)[csc];
+    // per-row factors of the thread's theta interface (fk) and cell (rk).  FP64
+    // keeps its tile's rows in LDS and reads each factor where it is used:
+    // held in registers they would cost a wave per SIMD (18 registers), and
+    // the FP64 kernel's throughput follows its occupancy
+    // (only the fields the variant uses: 4 or 5 face values, 5 cell values
+    // per row, which keeps five workgroups' LDS within a CU)
+    constexpr bool ROWS_LDS = sizeof(T) == 8;
+    constexpr int NFK = GEN ? 5 : 4, NRK = 5;
+    __shared__ T sfk[ROWS_LDS ? (TS + 1) * NFK : 1];
+    __shared__ T srk[ROWS_LDS ? TS * NRK : 1];
+    FaceRowK<T> fkr{};
+    CellRowK<T> rkr{};
+    if constexpr (ROWS_LDS) {
+        if (tid < TS + 1) {
+            const FaceRowK<T> f = static_cast<const FaceRowK<T>*>(D.facek)[s0 + tid < nt ? s0 + tid : nt];
+            T* o = sfk + tid * NFK;
+            o[0] = f.cp1; o[1] = f.cp3; o[2] = f.cm1; o[3] = f.cm3;
+            if constexpr (GEN) o[4] = f.sI;
+        } else if (tid >= 64 && tid < 64 + TS) {
+            const CellRowK<T> c = static_cast<const CellRowK<T>*>(D.rowk)[s0 + tid - 64 < nt ? s0 + tid - 64 : nt - 1];
+            T* o = srk + (tid - 64) * NRK;
+            o[0] = c.th_o; o[1] = c.th_i; o[2] = c.ph_o; o[3] = c.ph_i; o[4] = c.dtcot;
+        }
+    } else {
+        fkr = static_cast<const FaceRowK<T>*>(D.facek)[ig];
+        rkr = static_cast<const CellRowK<T>*>(D.rowk)[csc];
+    }
+    // face factor i of the thread's theta interface: cp1, cp3, cm1, cm3, sI
+    auto FK = [&](int i) -> T {
+        if constexpr (ROWS_LDS) return sfk[ti * NFK + i];
+        else return i == 0 ? fkr.cp1 : i == 1 ? fkr.cp3 : i == 2 ? fkr.cm1 : i == 3 ? fkr.cm3 : fkr.sI;
+    };
+    // cell factor i of the thread's row: th_o, th_i, ph_o, ph_i, dtcot
+    auto RK = [&](int i) -> T {
+        if constexpr (ROWS_LDS) return srk[cr * NRK + i];
+        else return i == 0 ? rkr.th_o : i == 1 ? rkr.th_i : i == 2 ? rkr.ph_o : i == 3 ? rkr.ph_i : rkr.dtcot;
+    };
     const T dti = uni<T>(D, U_DTI);
     const T epsk = uni<T>(D, U_EPSK);
     const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
@@ -532,20 +564,44 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     T drho = T(0), jt = T(0), jp = T(0);
     // the loop's uniform constants, read once into scalar registers so that the
     // population loop issues no scalar loads (whose waits would also wait for
-    // the outstanding LDS reads); the float force uses the kernels K^H, K~^H
-    // (32 values) instead of the 128 premultiplied fa, fb
-    T CK[NK], CKt[NK], Cwr[NK], Cv[NQ], Cnv2[NQ];
+    // the outstanding LDS reads).  The force uses the kernels K^H, K~^H, not
+    // their products with the node speeds.  FP64 keeps only the rows of the
+    // first (Q+1)/2 nodes, which fit the scalar registers: the nodes are
+    // symmetric (v_{Q-1-i} = -v_i, H_n(-x) = (-1)^n H_n(x)), so
+    // K^H[Q-1-i][Q-1-j] = -K^H[i][j], K~^H[Q-1-i][Q-1-j] = K~^H[i][j] and
+    // w_k depends on the folded node indices only.
+    constexpr bool FOLD = sizeof(T) == 8;
+    constexpr int NH = (NQ + 1) / 2;
+    constexpr int NKR = FOLD ? NH * NQ : NK, NVR = FOLD ? NH : NQ, NWR = FOLD ? NH * NH : NK;
+    T CK[NKR], CKt[NKR], Cwr[NWR], Cv[NVR], Cnv2[NVR];
 #pragma unroll
-    for (int i = 0; i < NK; ++i) { CK[i] = C.K[i]; CKt[i] = C.Kt[i]; Cwr[i] = C.wr[i]; }
+    for (int i = 0; i < NKR; ++i) { CK[i] = C.K[i]; CKt[i] = C.Kt[i]; }
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) { Cv[i] = C.v[i]; Cnv2[i] = C.nv2[i]; }
+    for (int i = 0; i < NWR; ++i) Cwr[i] = FOLD ? C.wr[(i / NH) * NQ + i % NH] : C.wr[i];
+#pragma unroll
+    for (int i = 0; i < NVR; ++i) { Cv[i] = C.v[i]; Cnv2[i] = C.nv2[i]; }
+    auto mir = [](int i) { return FOLD && 2 * i >= NQ; };
+    auto fold = [&](int i) { return mir(i) ? NQ - 1 - i : i; };
+    auto kK = [&](int i, int j) { return mir(i) ? -CK[fold(i) * NQ + NQ - 1 - j] : CK[i * NQ + j]; };
+    auto kKt = [&](int i, int j) { return mir(i) ? CKt[fold(i) * NQ + NQ - 1 - j] : CKt[i * NQ + j]; };
+    auto nodev = [&](int i) { return mir(i) ? -Cv[fold(i)] : Cv[i]; };
+    auto nodenv2 = [&](int i) { return Cnv2[fold(i)]; };
+    auto wrk = [&](int kt, int kp) { return FOLD ? Cwr[fold(kt) * NH + fold(kp)] : Cwr[kt * NQ + kp]; };
 
-    // Ring of three LDS slots: population p lives in slot p % 3.  Its global
-    // loads are issued at the start of iteration p - 2 and it is written to LDS
-    // after that iteration's barrier, when the slot of population p - 3 has been
-    // read for the last time.
+    // Ring of three LDS slots: population p lives in slot p % 3 and is written
+    // to LDS at the end of iteration p - 2, when the slot of population p - 3
+    // has been read for the last time.  Its global loads are issued PF
+    // iterations ahead, at the start of iteration p - PF, into the register
+    // pair nx[p % 2]: FP64 (4 waves per SIMD) gives them two iterations to
+    // arrive, the float kernels (7 waves) one.
+    constexpr int PF = sizeof(T) == 8 ? 3 : 2;
+    T nx[2][2];
     {
         const T a0 = gload(0, 0), a1 = gload(0, 1), b0 = gload(1, 0), b1 = gload(1, 1);
+        if constexpr (PF == 3) {
+            nx[0][0] = gload(2, 0);
+            nx[0][1] = gload(2, 1);
+        }
         lstore(0, 0, a0, a1);
         lstore(1, 1, b0, b1);
     }
@@ -558,11 +614,10 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
         // theta and phi speeds of this population (zero: no flux in that direction)
         const int st = vsgn(kt), sp = vsgn(kp);
         T gself = T(0), Ftself = T(0), Flself = T(0);
-        // global loads of population k+2 (written to LDS after the barrier)
-        T nx0 = T(0), nx1 = T(0);
-        if (k + 2 < NK) {
-            nx0 = gload(k + 2, 0);
-            nx1 = gload(k + 2, 1);
+        // global loads of population k+PF
+        if (k + PF < NK) {
+            nx[(k + PF) & 1][0] = gload(k + PF, 0);
+            nx[(k + PF) & 1][1] = gload(k + PF, 1);
         }
         // theta flux of sin(theta_j) g_j (the speed multiplies the difference)
         if (st != 0) {
@@ -578,14 +633,14 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             if constexpr (!UPW) {
                 if (st > 0)
                     F = weno5x6<T, true>(h[0], h[1], h[2], h[3], h[4], g[0], g[1], g[2], g[3], g[4],
-                                         epsk, Cwr[k], fk.cp1, fk.cp3);
+                                         epsk, wrk(kt, kp), FK(0), FK(1));
                 else
                     F = weno5x6<T, true>(h[5], h[4], h[3], h[2], h[1], g[5], g[4], g[3], g[2], g[1],
-                                         epsk, Cwr[k], fk.cm1, fk.cm3);
+                                         epsk, wrk(kt, kp), FK(2), FK(3));
             } else {
                 F = st > 0 ? upwind(scheme, h[1], h[2], h[3]) : upwind(scheme, h[4], h[3], h[2]);
             }
-            if constexpr (GEN) F *= fk.sI;
+            if constexpr (GEN) F *= FK(4);
             fth[fb][tid] = F;
             Ftself = F;                                  // top face of this thread's cell
         } else {
@@ -619,40 +674,33 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
             if constexpr (sizeof(T) == 8) a = fma(uni<T>(D, U_OMDTI), gc, a);
             if (st != 0) {                               // - v_theta dt/(R sin th dth) (F_b - F_t)
                 const T Fb = fth[fb][(cr + 1) * TQ + cc];
-                const T f = vouter(kt) ? rk.th_o : rk.th_i;
+                const T f = RK(vouter(kt) ? 0 : 1);
                 a = fma(st > 0 ? -f : f, Fb - Ftself, a);
             }
             if (sp != 0) {                               // - v_phi dt/(R sin th dph) (F_r - F_l)
                 const T Fr = fph[fb][rslot];
-                const T f = vouter(kp) ? rk.ph_o : rk.ph_i;
+                const T f = RK(vouter(kp) ? 2 : 3);
                 a = fma(sp > 0 ? -f : f, Fr - Flself, a);
             }
             acc[k] = a;
-            const T tg = rk.dtcot * gc;
-            if constexpr (sizeof(T) == 8) {
+            // rank-1 force updates: -v_kp^2 K[b][kt] and v_kt K~[b][kp] times
+            // dt cot(theta)/R g, applied as two scalings of tg
+            const T tg = RK(4) * gc;
+            const T ta = nodenv2(kp) * tg, tb = nodev(kt) * tg;
 #pragma unroll
-                for (int b = 0; b < NQ; ++b) {
-                    acc[b * NQ + kp] += C.fa[(kp * NQ + b) * NQ + kt] * tg;
-                    acc[kt * NQ + b] += C.fb[(kt * NQ + b) * NQ + kp] * tg;
-                }
-            } else {
-                // fa = -v_kp^2 K[b][kt], fb = v_kt K~[b][kp] applied as two scalings of tg
-                const T ta = Cnv2[kp] * tg, tb = Cv[kt] * tg;
-#pragma unroll
-                for (int b = 0; b < NQ; ++b) {
-                    acc[b * NQ + kp] = fma(CK[b * NQ + kt], ta, acc[b * NQ + kp]);
-                    acc[kt * NQ + b] = fma(CKt[b * NQ + kp], tb, acc[kt * NQ + b]);
-                }
+            for (int b = 0; b < NQ; ++b) {
+                acc[b * NQ + kp] = fma(kK(b, kt), ta, acc[b * NQ + kp]);
+                acc[kt * NQ + b] = fma(kKt(b, kp), tb, acc[kt * NQ + b]);
             }
             if constexpr (sizeof(T) != 8) {
                 gk[k] = gc;                          // moments from these at the end
             } else {
                 drho += gc;
-                jt += C.v[kt] * gc;
-                jp += C.v[kp] * gc;
+                jt = fma(nodev(kt), gc, jt);
+                jp = fma(nodev(kp), gc, jp);
             }
         }
-        if (k + 2 < NK) lstore(k + 2, (k + 2) % 3, nx0, nx1);
+        if (k + 2 < NK) lstore(k + 2, (k + 2) % 3, nx[k & 1][0], nx[k & 1][1]);
         // keep this population's register arithmetic in place: deferring it past
         // the following barriers would keep every population's inputs live at once
         if constexpr (NK == 16)
@@ -1167,12 +1215,15 @@ void build_consts(Consts& c, int storage, int q) {
             c.K[i * q + j] = -w1[i] * a;
             c.Kt[i * q + j] = -w1[i] * b;
         }
-    for (int kt = 0; kt < q; ++kt)
-        for (int kp = 0; kp < q; ++kp)
-            for (int a = 0; a < q; ++a) {
-                c.fa[(kp * q + a) * q + kt] = -c.v[kp] * c.v[kp] * c.K[a * q + kt];
-                c.fb[(kt * q + a) * q + kp] = c.v[kt] * c.Kt[a * q + kp];
-            }
+    // the rows of the nodes past the middle follow from the symmetric nodes
+    // (H_n(-x) = (-1)^n H_n(x)): K^H[q-1-i][q-1-j] = -K^H[i][j] and
+    // K~^H[q-1-i][q-1-j] = K~^H[i][j].  The recurrence already gives these
+    // values; setting them makes the symmetry the stage kernel relies on exact.
+    for (int i = (q + 1) / 2; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+            c.K[i * q + j] = -c.K[(q - 1 - i) * q + (q - 1 - j)];
+            c.Kt[i * q + j] = c.Kt[(q - 1 - i) * q + (q - 1 - j)];
+        }
     for (int k = 0; k < q * q; ++k) {
         double sc = 1.0;
         if (storage == VLBM_STORE_F16_DEV) sc = std::ldexp(1.0, 10 - (int)std::lround(std::log2(c.wk[k])));
@@ -1661,10 +1712,6 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
         x->cf.wr[k] = fv[k / q] != 0.f ? (float)(vw / (double)fv[k / q]) : 0.f;
         x->cd.scale[k] = x->c.scale[k]; x->cf.scale[k] = (float)x->c.scale[k];
         x->cd.iscale[k] = x->c.iscale[k]; x->cf.iscale[k] = (float)x->c.iscale[k];
-    }
-    for (int i = 0; i < q * q * q; ++i) {
-        x->cd.fa[i] = x->c.fa[i]; x->cf.fa[i] = (float)x->c.fa[i];
-        x->cd.fb[i] = x->c.fb[i]; x->cf.fb[i] = (float)x->c.fb[i];
     }
     for (int i = 0; i < q * q; ++i) {
         x->cd.K[i] = x->c.K[i]; x->cf.K[i] = (float)x->c.K[i];
