@@ -133,8 +133,10 @@ def run_ensemble(steps):
     deviation store, tau = nu drawn uniformly in [1e-4, 1e-2] and an axisymmetric
     shock (rho = 1.5, T = 1.2 for theta < theta0, theta0 uniform in [pi/6, pi/3])
     per run, seed 0 (draws (nu, theta0) in run order); dt per run from the
-    stability rule.  Times `steps` steps one run at a time, batched, and batched
-    from a HIP graph after the autotuner (launch grouping x tile shape)."""
+    stability rule.  Times `steps` steps one run at a time, batched, batched
+    from a HIP graph after the autotuner (launch grouping x tile shape), and
+    in persistent launches (one per launch group of the tuned configuration,
+    and one for all 64 runs with 15 x 16 tiles)."""
     import torch
     import workloads as W
     from paper_2504_15574_amd import Ensemble, Solver
@@ -182,8 +184,14 @@ def run_ensemble(steps):
     e1.record(sols[0].stream)
     torch.cuda.synchronize()
     gr = e0.elapsed_time(e1)
-    finite = all(s.diagnostics(raise_unstable=False)[4] == 0 for s in sols)
     ens.release()
+    # persistent: one cooperative launch per launch group carries all steps
+    per_tuned = timed(lambda n: ens.step(n, persistent=True))
+    tuned = (ens.grouping, ens.tile)
+    ens.configure("all", (15, 16))
+    per_all = timed(lambda n: ens.step(n, persistent=True))
+    ens.configure(*tuned)
+    finite = all(s.diagnostics(raise_unstable=False)[4] == 0 for s in sols)
     for s in sols:
         s.close()
     mlups = lambda ms: round(cells * steps / (ms * 1e-3) / 1e6, 1)
@@ -192,7 +200,9 @@ def run_ensemble(steps):
             "tile": ens.tile_name(),
             "autotune_ms_per_step": {k: round(v, 4) for k, v in tune.items()},
             "mlups_one_run_per_launch": mlups(one), "mlups_batched": mlups(bat),
-            "mlups_batched_graph": mlups(gr), "finite": finite}
+            "mlups_batched_graph": mlups(gr),
+            "mlups_persistent": mlups(per_tuned), "mlups_persistent_one_launch": mlups(per_all),
+            "finite": finite}
 
 
 def cpu_baseline(state, threads):

@@ -181,6 +181,26 @@ typedef struct vlbm_graph vlbm_graph;
  * Asynchronous on the shared stream.  Errors: VLBM_ERR_ARG. */
 vlbm_status vlbm_step_batch(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps);
 
+/* The same steps as vlbm_step_batch in one persistent launch per 64
+ * contexts: a cooperative kernel whose co-resident workgroups take the tiles
+ * of every RK stage in turn and meet at a grid-wide barrier between stages
+ * (SSP-RK3, Sec. III.G: stage s+1 reads stage s over every halo).  Results
+ * equal vlbm_step_batch and vlbm_step bit for bit.  The contexts must use
+ * D2Q16 and the standard WENO-5 form (VLBM_ADV_WENO5), besides sharing what
+ * vlbm_step_batch requires; the barrier count lives in the first context's
+ * workspace, so two persistent calls on the same first context must not
+ * overlap.  Synchronous: returns after the launch has finished.  Each
+ * barrier wait is bounded (vlbm_set_barrier_spin_limit); a wait that gives up
+ * (a grid that was not co-resident) leaves the runs' state undefined and
+ * returns VLBM_ERR_DEVICE.  Errors: VLBM_ERR_ARG, VLBM_ERR_DEVICE. */
+vlbm_status vlbm_step_batch_persistent(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps);
+
+/* Polls of one grid-barrier wait before vlbm_step_batch_persistent gives up
+ * (default 2^20, about a second; one stage takes milliseconds).  Process-wide.
+ * A tiny limit makes the waits give up, which tests use to check the error
+ * path without stalling the device. */
+vlbm_status vlbm_set_barrier_spin_limit(uint32_t polls);
+
 /* Record n_steps >= 1 of vlbm_step_batch(ctxs, n_ctx, .) into a HIP graph
  * (captured on a private stream; nothing runs now).  The graph refers to the
  * contexts' workspaces: destroy it before them.  Errors: VLBM_ERR_ARG,

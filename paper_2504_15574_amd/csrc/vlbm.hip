@@ -317,15 +317,13 @@ __device__ __forceinline__ int wrap1(int q, int np) {
 // exactly once and exchanged through LDS.  Populations are processed one at a
 // time; each population's tile with its 3-cell cross-shaped halo (pole rows
 // gathered from column q + np/2 and population 15 - k, phi periodic) sits in a
-// triple-buffered LDS slot, so the global loads of population k+2 overlap the
-// fluxes of population k and one barrier per population suffices.  The 240
+// triple-buffered LDS slot, so the global loads of the next populations
+// overlap the fluxes of population k and one barrier per population suffices.
+// The 240
 // cell threads accumulate dt*L for all 16 populations in registers, starting
 // from the rest-state table: advection and the rank-1 updates of the inertial
 // force (FP64 also -g/tau); the equilibrium is added at the end from the
 // moments (FP64: running sums; float: sums of the 16 inputs kept in registers).
-// Workgroups are numbered so that those sharing an XCD (dispatched round-robin
-// over the 8 XCDs) take a contiguous range of tiles, keeping halo rows and the
-// 64-byte halves of shared cache lines inside one L2.
 // Two tile shapes fit this thread mapping ((TS + 1) TQ theta interfaces = 256
 // threads, at most two cross-shaped loads per thread): 15 x 16 (the default,
 // least halo per cell) and 7 x 32 (fewer rows, for grids whose row count 15
@@ -382,8 +380,12 @@ enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
 // 32 KB per workgroup, also allows no more).
 template <class T, int VAR>
 constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
-template <class St, bool BATCH, class Tl, int VAR, int NQ>
-__global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) void stage_kernel(StageArgs A) {
+// One tile of one run at one RK stage: tile t of the run described by D, whose
+// reduced-precision stores take the dither phase of step ctr.  Every thread of
+// the workgroup calls it; it ends after its last barrier (threads without a
+// cell return before the epilogue).
+template <class St, class Tl, int VAR, int NQ>
+__device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D, int t, uint32_t ctr) {
     constexpr bool GEN = VAR != VAR_WENO, UPW = VAR == VAR_UPWIND;
     constexpr int NK = NQ * NQ;
     constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR;
@@ -401,23 +403,6 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
 
     const ConstsT<T>& C = consts_of<T>(A);
     const int tid = threadIdx.x;
-    const int nall = A.tile_start[A.nruns];
-    const int per = (nall + 7) / 8;
-    const int tg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tg >= nall) return;                    // whole workgroup leaves before any barrier
-    // a single-run launch reads its run from the kernel arguments; a batched one
-    // looks up the run this tile belongs to (uniform per workgroup)
-    int run = 0;
-    if (BATCH) {                               // largest run with tile_start[run] <= tg
-        int hi = A.nruns - 1;
-        while (run < hi) {
-            const int mid = (run + hi + 1) >> 1;
-            if (A.tile_start[mid] <= tg) run = mid;
-            else hi = mid - 1;
-        }
-    }
-    const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
-    const int t = tg - A.tile_start[run];
     const int nt = D.nt, np = D.np;
     const int tq = (np + TQ - 1) / TQ;
     const int s0 = (t / tq) * TS, q0 = (t % tq) * TQ;
@@ -786,7 +771,7 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     //    graph-replayed steps give identical bits.
     uint32_t hsh = 0;
     if constexpr (sizeof(T) != 8) {
-        hsh = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) ^ (*D.ctr * 0x9E3779B9u + D.seq * 0x85EBCA6Bu);
+        hsh = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) ^ (ctr * 0x9E3779B9u + D.seq * 0x85EBCA6Bu);
         hsh ^= hsh >> 16; hsh *= 0x7feb352du;
         hsh ^= hsh >> 15; hsh *= 0x846ca68bu;
         hsh ^= hsh >> 16;
@@ -823,6 +808,123 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
         finish(NK - 1 - k, base - ro);
     }
     if constexpr (NK & 1) finish(NK / 2, fma(rho, ev0, drho));     // xi = 0
+}
+
+// the run of global tile tg: the largest run with tile_start[run] <= tg
+__device__ __forceinline__ int run_of(const StageArgs& A, int tg) {
+    int run = 0, hi = A.nruns - 1;
+    while (run < hi) {
+        const int mid = (run + hi + 1) >> 1;
+        if (A.tile_start[mid] <= tg) run = mid;
+        else hi = mid - 1;
+    }
+    return run;
+}
+
+// One RK stage over the tiles of up to MAXRUNS runs, one workgroup per tile.
+// Workgroups are numbered so that those sharing an XCD (dispatched round-robin
+// over the 8 XCDs) take a contiguous range of tiles, keeping halo rows and the
+// 64-byte halves of shared cache lines inside one L2.  A single-run launch reads
+// its run from the kernel arguments; a batched one looks up the run of its
+// tile (uniform per workgroup).
+template <class St, bool BATCH, class Tl, int VAR, int NQ>
+__global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) void stage_kernel(StageArgs A) {
+    const int nall = A.tile_start[A.nruns];
+    const int per = (nall + 7) / 8;
+    const int tg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tg >= nall) return;                    // whole workgroup leaves before any barrier
+    const int run = BATCH ? run_of(A, tg) : 0;
+    const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
+    const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr;
+    stage_tile<St, Tl, VAR, NQ>(A, D, tg - A.tile_start[run], ctr);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched stepping: one cooperative launch carries n steps (3n RK
+// stages) of up to MAXRUNS runs.  Its workgroups are co-resident; each takes
+// the tiles of a stage with the XCD-aware numbering of stage_kernel, strided
+// by the grid size (a multiple of 8, so a workgroup stays on its XCD's range),
+// and all meet at a grid barrier before the next stage reads the halos.  The tile arithmetic is stage_tile's, so the results equal per-stage
+// launches bit for bit.
+struct PersistArgs {
+    StageArgs A;           // desc[i]: run i's stage-1 descriptor; stages 2 and 3 follow it
+    int nsteps;
+    uint32_t spin_limit;   // polls of one barrier wait before it gives up
+    uint32_t* bar;         // arrivals at the grid barrier, zero at the launch
+    uint32_t* err;         // set to 1 when a barrier wait gave up
+};
+static_assert(sizeof(PersistArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
+
+// Grid barrier: every workgroup adds one arrival (release at device scope, so
+// its stores reach the other XCDs) and polls the count with relaxed loads
+// until it reaches target; one acquire fence then makes the other workgroups'
+// stores visible to its later loads.  (An acquire on every poll would
+// invalidate the XCD's caches under the workgroups still computing.)  The
+// wait is bounded: after spin_limit polls, or once another workgroup has
+// given up, it sets err and returns, so a grid that is not co-resident still
+// ends.
+__device__ __forceinline__ void grid_barrier(const PersistArgs& P, uint32_t target) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(P.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(P.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > P.spin_limit || __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(P.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(32);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// A run descriptor as workgroup-uniform values.  The kernel stores to memory,
+// so the compiler cannot keep the descriptor loads scalar and would treat
+// everything built from them (buffer resources, run constants) as per-lane
+// values; every word is the same on all lanes, so the first lane's is taken.
+__device__ __forceinline__ RunDesc uniform_desc(const RunDesc* p) {
+    static_assert(sizeof(RunDesc) % 4 == 0, "descriptor words");
+    RunDesc d;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+    uint32_t w[sizeof(RunDesc) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(RunDesc) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    __builtin_memcpy(&d, w, sizeof(RunDesc));
+    return d;
+}
+
+template <class St, class Tl>
+__global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR_WENO>())) void persist_kernel(PersistArgs P) {
+    const StageArgs& A = P.A;
+    const int nall = A.tile_start[A.nruns];
+    const int per = (nall + 7) / 8;
+    const int G = (int)gridDim.x;
+    uint32_t target = 0;
+    for (int step = 0; step < P.nsteps; ++step) {
+        for (int stage = 0; stage < 3; ++stage) {
+            for (int vb = (int)blockIdx.x; vb < 8 * per; vb += G) {
+                const int tg = (vb & 7) * per + (vb >> 3);
+                if (tg < nall) {                       // uniform per workgroup
+                    const int run = run_of(A, tg);
+                    const RunDesc D = uniform_desc(A.desc[run] + stage);
+                    const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr + (uint32_t)step;
+                    stage_tile<St, Tl, VAR_WENO, 4>(A, D, tg - A.tile_start[run], ctr);
+                }
+                __syncthreads();                       // the tile's LDS is free again
+            }
+            target += (uint32_t)G;
+            grid_barrier(P, target);
+        }
+    }
+    // after the last barrier every tile has read the step counters
+    if (sizeof(typename St::T) != 8 && blockIdx.x == 0 && (int)threadIdx.x < A.nruns)
+        const_cast<uint32_t*>(A.desc[threadIdx.x]->ctr)[0] += (uint32_t)P.nsteps;
+}
+
+__global__ __launch_bounds__(64) void persist_reset_kernel(uint32_t* bar) {
+    if (threadIdx.x < 2) bar[threadIdx.x] = 0u;       // count, error flag
 }
 
 // ---------------------------------------------------------------------------
@@ -1328,7 +1430,7 @@ constexpr int RED_BLOCKS = 1024;
 
 struct Layout {
     size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, sI, rowk, rowk_f, facek, facek_f;
-    size_t fields, part, dout, desc, ctr, total;
+    size_t fields, part, dout, desc, ctr, bar, total;
 };
 
 Layout layout_of(const vlbm_params& p) {
@@ -1355,6 +1457,7 @@ Layout layout_of(const vlbm_params& p) {
     L.dout = off; off += align_up(sizeof(double) * 8);
     L.desc = off; off += align_up(sizeof(RunDesc) * 3);
     L.ctr = off; off += align_up(sizeof(uint32_t));
+    L.bar = off; off += align_up(2 * sizeof(uint32_t));   // grid barrier count, error flag
     L.total = off;
     return L;
 }
@@ -1614,6 +1717,63 @@ vlbm_status step_batch(vlbm_ctx* const* xs, int n, int64_t n_steps, hipStream_t 
     return VLBM_OK;
 }
 
+// Polls of one grid-barrier wait before the persistent kernel gives up (about
+// a second at the default; a stage takes about a millisecond).
+uint32_t g_spin_limit = 1u << 20;
+
+// Persistent stepping of up to MAXRUNS contexts of one storage format (WENO-5
+// standard form, Q = 4).  Synchronous: waits for the launch to read the
+// barrier's error flag.
+template <class St>
+vlbm_status persist_group(vlbm_ctx* const* xs, int m, int64_t nsteps, hipStream_t stream) {
+    PersistArgs P{};
+    StageArgs& A = P.A;
+    A.cd = xs[0]->cd;
+    A.cf = xs[0]->cf;
+    A.nruns = m;
+    A.tile_start[0] = 0;
+    for (int i = 0; i < m; ++i) {
+        A.desc[i] = desc_of(xs[i], 1);
+        A.tile_start[i + 1] = A.tile_start[i] + n_tiles(xs[i]->p.n_theta, xs[i]->p.n_phi, xs[i]->tile);
+    }
+    const int nall = A.tile_start[m];
+    const void* fn = xs[0]->tile == 1 ? reinterpret_cast<const void*>(persist_kernel<St, Tile7x32>)
+                                      : reinterpret_cast<const void*>(persist_kernel<St, Tile15x16>);
+    // co-resident workgroups: the runtime's occupancy, capped by the LDS a CU
+    // was measured to hold for five 32 KiB workgroups (not all of its 160 KiB)
+    int ncu = 0, occ = 0;
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, xs[0]->device));
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, NTHR, 0));
+    hipFuncAttributes fa{};
+    HIP_OK(hipFuncGetAttributes(&fa, fn));
+    if (fa.sharedSizeBytes > 0) occ = std::min<int>(occ, (int)(159744 / fa.sharedSizeBytes));
+    const int per = (nall + 7) / 8;
+    const int G = std::min(8 * ((occ * ncu) / 8), 8 * per);
+    if (G < 8) return fail(VLBM_ERR_DEVICE, "no co-resident grid for the persistent stage kernel");
+    P.bar = at<uint32_t>(xs[0], xs[0]->L.bar);
+    P.err = P.bar + 1;
+    P.spin_limit = g_spin_limit;
+    // one launch carries at most as many steps as the 32-bit arrival count allows
+    const int64_t chunk = std::min<int64_t>(INT32_MAX, (int64_t)(0xffffffffu / (3u * (uint32_t)G)));
+    for (int64_t done = 0; done < nsteps;) {
+        P.nsteps = (int)std::min(nsteps - done, chunk);
+        hipLaunchKernelGGL(persist_reset_kernel, dim3(1), dim3(64), 0, stream, P.bar);
+        vlbm_status st = launch_check();
+        if (st) return st;
+        void* args[] = {&P};
+        HIP_OK(hipLaunchCooperativeKernel(fn, dim3(G), dim3(NTHR), args, 0, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        uint32_t err = 0;
+        HIP_OK(hipMemcpy(&err, P.err, sizeof(err), hipMemcpyDeviceToHost));
+        if (err)
+            return fail(VLBM_ERR_DEVICE, "persistent stepping: a grid barrier wait gave up after %u polls; "
+                        "the runs' state is undefined", P.spin_limit);
+        done += P.nsteps;
+    }
+    for (int i = 0; i < m; ++i) xs[i]->launches += 3 * nsteps;
+    return VLBM_OK;
+}
+
 vlbm_status copy_in(vlbm_ctx* x, double* dst, const double* src, size_t n, int on_dev) {
     HIP_OK(hipMemcpyAsync(dst, src, n * sizeof(double),
                           on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, x->stream));
@@ -1836,6 +1996,29 @@ vlbm_status vlbm_step_batch(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps) {
     if (st) return st;
     if (n_steps < 0) return fail(VLBM_ERR_ARG, "n_steps < 0");
     return step_batch(ctxs, n_ctx, n_steps, ctxs[0]->stream);
+}
+
+vlbm_status vlbm_step_batch_persistent(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps) {
+    vlbm_status st = check_batch(ctxs, n_ctx);
+    if (st) return st;
+    if (n_steps < 0) return fail(VLBM_ERR_ARG, "n_steps < 0");
+    for (int i = 0; i < n_ctx; ++i)
+        if (ctxs[i]->p.q != 4 || ctxs[i]->p.advection != VLBM_ADV_WENO5)
+            return fail(VLBM_ERR_ARG, "persistent stepping needs D2Q16 with the standard WENO-5 form (context %d)", i);
+    if (n_steps == 0) return VLBM_OK;
+    for (int c0 = 0; c0 < n_ctx; c0 += MAXRUNS) {
+        const int m = std::min(MAXRUNS, n_ctx - c0);
+        st = dispatch(ctxs[0]->p.storage, [&](auto tag) {
+            return persist_group<decltype(tag)>(ctxs + c0, m, n_steps, ctxs[0]->stream);
+        });
+        if (st) return st;
+    }
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_set_barrier_spin_limit(uint32_t polls) {
+    g_spin_limit = polls;
+    return VLBM_OK;
 }
 
 vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps, vlbm_graph** out) {

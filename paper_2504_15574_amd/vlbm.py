@@ -63,6 +63,8 @@ SIGNATURES = [
     ("vlbm_correct_moments", ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int]),
     ("vlbm_set_tile_shape", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     ("vlbm_step_batch", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64]),
+    ("vlbm_step_batch_persistent", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64]),
+    ("vlbm_set_barrier_spin_limit", ctypes.c_int, [ctypes.c_uint32]),
     ("vlbm_graph_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
                                          ctypes.POINTER(_vp)]),
     ("vlbm_graph_launch", ctypes.c_int, [_vp]),
@@ -191,6 +193,15 @@ def _ctx_array(ctxs):
 
 def vlbm_step_batch(ctxs, n: int):
     _check(load().vlbm_step_batch(_ctx_array(ctxs), len(ctxs), int(n)), "vlbm_step_batch")
+
+
+def vlbm_step_batch_persistent(ctxs, n: int):
+    _check(load().vlbm_step_batch_persistent(_ctx_array(ctxs), len(ctxs), int(n)),
+           "vlbm_step_batch_persistent")
+
+
+def vlbm_set_barrier_spin_limit(polls: int):
+    _check(load().vlbm_set_barrier_spin_limit(int(polls)), "vlbm_set_barrier_spin_limit")
 
 
 def vlbm_graph_create(ctxs, n: int) -> int:
@@ -399,9 +410,15 @@ class Ensemble:
     def set_grouping(self, grouping):
         self.configure(grouping=grouping)
 
-    def step(self, n=1):
+    def step(self, n=1, persistent=False):
+        """n steps of every run; ``persistent``: one cooperative launch per
+        launch group carries all n steps (``vlbm_step_batch_persistent``;
+        D2Q16, standard WENO-5 form; returns when done)."""
         for g in self.groups:
-            vlbm_step_batch(g, n)
+            if persistent:
+                vlbm_step_batch_persistent(g, n)
+            else:
+                vlbm_step_batch(g, n)
         for s in self.solvers:
             s.t += n * s.dt
 

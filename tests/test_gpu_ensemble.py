@@ -189,3 +189,74 @@ def test_autotuner_per_size_tiles_keep_the_bits():
         assert np.array_equal(s.populations(), r.populations())
     for s in runs + ref:
         s.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_persistent_launch_equals_one_by_one_bitwise(storage):
+    # one cooperative launch carries all 7 steps of the six runs (grid
+    # barriers between the RK stages); every cell must equal stepping each run
+    # alone, and the step counters (dither phase) must advance the same way
+    from paper_2504_15574_amd import Ensemble, vlbm_stage_launches
+    a = _runs(storage, SPECS, seed=21)
+    b = _runs(storage, SPECS, seed=21)
+    Ensemble(a).step(7, persistent=True)
+    for s in b:
+        s.step(7)
+    for x, y in zip(a, b):
+        assert vlbm_stage_launches(x.ctx) == 21
+        assert np.array_equal(x.populations(), y.populations())
+    Ensemble(a).step(2, persistent=True)           # a second launch continues the runs
+    for s in b:
+        s.step(2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.populations(), y.populations())
+    for s in a + b:
+        s.close()
+
+
+def test_persistent_launch_many_runs_and_wide_tiles():
+    from paper_2504_15574_amd import Ensemble
+    specs = [(8, 16)] * 40 + [(12, 32)] * 30 + [(37, 70)]
+    a = _runs("f32", specs, seed=22)
+    b = _runs("f32", specs, seed=22)
+    Ensemble(a, tile=(7, 32)).step(3, persistent=True)
+    for s in b:
+        s.step(3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.populations(), y.populations())
+    for s in a + b:
+        s.close()
+
+
+def test_persistent_launch_rejects_other_kernels():
+    from paper_2504_15574_amd import Solver, VlbmError, vlbm_step_batch_persistent
+    s9 = Solver(16, 32, 2e-3, q=3)
+    sk = Solver(16, 32, 2e-3, komissarov=True)
+    for s in (s9, sk):
+        s.init_fields(*W.random_state(16, 32, seed=1, du=0.05))
+        with pytest.raises(VlbmError):
+            vlbm_step_batch_persistent([s.ctx], 1)
+        s.close()
+
+
+def test_persistent_barrier_wait_gives_up_with_an_error():
+    # A spin limit of 0 makes every barrier wait give up at once: the kernel
+    # still runs to its end, and the call reports the undefined state.  The
+    # default limit then steps correctly again.
+    from paper_2504_15574_amd import VlbmError, vlbm_set_barrier_spin_limit, vlbm_step_batch_persistent
+    a = _runs("f32", [(32, 64), (48, 96)], seed=23)
+    b = _runs("f32", [(32, 64), (48, 96)], seed=23)
+    vlbm_set_barrier_spin_limit(0)
+    try:
+        with pytest.raises(VlbmError):
+            vlbm_step_batch_persistent([s.ctx for s in a], 2)
+    finally:
+        vlbm_set_barrier_spin_limit(1 << 20)
+    c = _runs("f32", [(32, 64), (48, 96)], seed=23)
+    vlbm_step_batch_persistent([s.ctx for s in c], 2)
+    for s in b:
+        s.step(2)
+    for x, y in zip(c, b):
+        assert np.array_equal(x.populations(), y.populations())
+    for s in a + b + c:
+        s.close()
