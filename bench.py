@@ -205,6 +205,20 @@ def run_ensemble(steps):
             "finite": finite}
 
 
+def host_info():
+    """The host the CPU baseline ran on: CPU model, logical CPUs, CPUs usable here."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(state, threads):
     import oracle
 
@@ -428,6 +442,7 @@ def main():
         threads = min(16, len(os.sched_getaffinity(0)))
         print(f"[bench] CPU oracle baseline on {threads} threads ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(state, threads)
+        out["host"] = host_info()
     print(json.dumps(out), flush=True)
 
 
