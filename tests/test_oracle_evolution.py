@@ -262,6 +262,28 @@ def test_vorticity_of_rigid_rotation():
     assert np.abs(om - 0.6 * np.cos(th)[:, None]).max() < 1e-5
 
 
+def test_vorticity_of_a_spherical_harmonic_converges_at_fourth_order():
+    # Streamfunction psi = P_3^2(cos th) cos(2 phi) with P_3^2(x) = 15 x (1 - x^2):
+    # u_th = -(1/sin th) d psi/d phi, u_phi = d psi/d th (R = 1), whose vorticity
+    # is the Laplacian of psi, -l (l + 1) psi = -12 psi (Sec. IV.D).  The
+    # oracle's central differences (with the pole-mirrored rows) must approach
+    # it at fourth order, including the rows next to the poles.
+    def err(nt):
+        nph = 2 * nt
+        th, ph = W.grid(nt, nph)
+        T, P = np.meshgrid(th, ph, indexing="ij")
+        x = np.cos(T)
+        p32, dp32 = 15 * x * (1 - x * x), 15 * (1 - 3 * x * x)
+        psi = p32 * np.cos(2 * P)
+        ut = 2 * p32 * np.sin(2 * P) / np.sin(T)
+        up = -np.sin(T) * dp32 * np.cos(2 * P)
+        om = oracle.vorticity(ut, up)
+        return np.abs(om + 12 * psi).max() / np.abs(12 * psi).max()
+    e1, e2 = err(32), err(64)
+    assert e1 < 2e-3
+    assert e1 / e2 > 12                                 # 16 for fourth order
+
+
 def test_diagnostics_of_rest_state():
     nt, nph, R = 16, 8, 1.0
     d = oracle.diagnostics(_rest(nt, nph) * 1.2, R)
