@@ -136,7 +136,8 @@ def run_ensemble(steps):
     stability rule.  Times `steps` steps one run at a time, batched, batched
     from a HIP graph after the autotuner (launch grouping x tile shape), and
     in persistent launches (one per launch group of the tuned configuration,
-    and one for all 64 runs with 15 x 16 tiles)."""
+    and one for all 64 runs with 15 x 16 tiles, also replayed from a HIP
+    graph)."""
     import torch
     import workloads as W
     from paper_2504_15574_amd import Ensemble, Solver
@@ -190,6 +191,10 @@ def run_ensemble(steps):
     tuned = (ens.grouping, ens.tile)
     ens.configure("all", (15, 16))
     per_all = timed(lambda n: ens.step(n, persistent=True))
+    # the same single persistent launch recorded in a HIP graph
+    ens.capture(steps, persistent=True)
+    per_graph = timed(lambda n: (ens.replay(), ens.check()))
+    ens.release()
     ens.configure(*tuned)
     finite = all(s.diagnostics(raise_unstable=False)[4] == 0 for s in sols)
     for s in sols:
@@ -202,6 +207,7 @@ def run_ensemble(steps):
             "mlups_one_run_per_launch": mlups(one), "mlups_batched": mlups(bat),
             "mlups_batched_graph": mlups(gr),
             "mlups_persistent": mlups(per_tuned), "mlups_persistent_one_launch": mlups(per_all),
+            "mlups_persistent_graph": mlups(per_graph),
             "finite": finite}
 
 

@@ -208,8 +208,25 @@ vlbm_status vlbm_set_barrier_spin_limit(uint32_t polls);
 vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps,
                               vlbm_graph** out);
 
+/* Record n_steps >= 1 of vlbm_step_batch_persistent(ctxs, n_ctx, .) into a HIP
+ * graph: per 64 contexts a kernel that clears the barrier state and the
+ * persistent stage kernel, as ordinary kernel nodes (no memset nodes).  In
+ * the graph the persistent launch is not cooperative: its grid is what the
+ * CUs hold at once, so it is co-resident while nothing else runs on the
+ * device, and a barrier wait that gives up is reported by vlbm_graph_check.
+ * The contexts' constraints are those of vlbm_step_batch_persistent.  Errors:
+ * as vlbm_graph_create. */
+vlbm_status vlbm_graph_create_persistent(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps,
+                                         vlbm_graph** out);
+
 /* Replay the recorded steps on the contexts' stream (asynchronous). */
 vlbm_status vlbm_graph_launch(vlbm_graph* graph);
+
+/* Wait for the graph's last replay and report whether a persistent launch in
+ * it gave up at a grid barrier (VLBM_ERR_DEVICE; the runs' state is then
+ * undefined).  Synchronises the contexts' stream.  VLBM_OK for graphs of
+ * vlbm_graph_create once their work has finished.  Errors: VLBM_ERR_ARG. */
+vlbm_status vlbm_graph_check(vlbm_graph* graph);
 
 /* Release the graph (not the contexts). */
 vlbm_status vlbm_graph_destroy(vlbm_graph* graph);

@@ -1507,6 +1507,7 @@ struct vlbm_ctx {
 
 struct vlbm_graph {
     std::vector<vlbm_ctx*> ctxs;
+    std::vector<const uint32_t*> errs;   // persistent graphs: the barrier error flag of each launch group
     int64_t steps = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1724,8 +1725,11 @@ uint32_t g_spin_limit = 1u << 20;
 // Persistent stepping of up to MAXRUNS contexts of one storage format (WENO-5
 // standard form, Q = 4).  Synchronous: waits for the launch to read the
 // barrier's error flag.
+// recording: the launches go into a HIP graph being captured on stream; they
+// are then ordinary kernel nodes (co-resident by the grid size when nothing
+// else runs on the device), and the error flag is read by vlbm_graph_check.
 template <class St>
-vlbm_status persist_group(vlbm_ctx* const* xs, int m, int64_t nsteps, hipStream_t stream) {
+vlbm_status persist_group(vlbm_ctx* const* xs, int m, int64_t nsteps, hipStream_t stream, bool recording) {
     PersistArgs P{};
     StageArgs& A = P.A;
     A.cd = xs[0]->cd;
@@ -1761,6 +1765,11 @@ vlbm_status persist_group(vlbm_ctx* const* xs, int m, int64_t nsteps, hipStream_
         vlbm_status st = launch_check();
         if (st) return st;
         void* args[] = {&P};
+        if (recording) {
+            HIP_OK(hipLaunchKernel(fn, dim3(G), dim3(NTHR), args, 0, stream));
+            done += P.nsteps;
+            continue;
+        }
         HIP_OK(hipLaunchCooperativeKernel(fn, dim3(G), dim3(NTHR), args, 0, stream));
         HIP_OK(hipStreamSynchronize(stream));
         uint32_t err = 0;
@@ -1770,7 +1779,24 @@ vlbm_status persist_group(vlbm_ctx* const* xs, int m, int64_t nsteps, hipStream_
                         "the runs' state is undefined", P.spin_limit);
         done += P.nsteps;
     }
-    for (int i = 0; i < m; ++i) xs[i]->launches += 3 * nsteps;
+    if (!recording)
+        for (int i = 0; i < m; ++i) xs[i]->launches += 3 * nsteps;
+    return VLBM_OK;
+}
+
+// Persistent stepping of contexts already checked by check_batch.
+vlbm_status step_persistent(vlbm_ctx* const* xs, int n, int64_t n_steps, hipStream_t stream, bool recording) {
+    for (int i = 0; i < n; ++i)
+        if (xs[i]->p.q != 4 || xs[i]->p.advection != VLBM_ADV_WENO5)
+            return fail(VLBM_ERR_ARG, "persistent stepping needs D2Q16 with the standard WENO-5 form (context %d)", i);
+    if (n_steps == 0) return VLBM_OK;
+    for (int c0 = 0; c0 < n; c0 += MAXRUNS) {
+        const int m = std::min(MAXRUNS, n - c0);
+        vlbm_status st = dispatch(xs[0]->p.storage, [&](auto tag) {
+            return persist_group<decltype(tag)>(xs + c0, m, n_steps, stream, recording);
+        });
+        if (st) return st;
+    }
     return VLBM_OK;
 }
 
@@ -2002,18 +2028,7 @@ vlbm_status vlbm_step_batch_persistent(vlbm_ctx* const* ctxs, int n_ctx, int64_t
     vlbm_status st = check_batch(ctxs, n_ctx);
     if (st) return st;
     if (n_steps < 0) return fail(VLBM_ERR_ARG, "n_steps < 0");
-    for (int i = 0; i < n_ctx; ++i)
-        if (ctxs[i]->p.q != 4 || ctxs[i]->p.advection != VLBM_ADV_WENO5)
-            return fail(VLBM_ERR_ARG, "persistent stepping needs D2Q16 with the standard WENO-5 form (context %d)", i);
-    if (n_steps == 0) return VLBM_OK;
-    for (int c0 = 0; c0 < n_ctx; c0 += MAXRUNS) {
-        const int m = std::min(MAXRUNS, n_ctx - c0);
-        st = dispatch(ctxs[0]->p.storage, [&](auto tag) {
-            return persist_group<decltype(tag)>(ctxs + c0, m, n_steps, ctxs[0]->stream);
-        });
-        if (st) return st;
-    }
-    return VLBM_OK;
+    return step_persistent(ctxs, n_ctx, n_steps, ctxs[0]->stream, false);
 }
 
 vlbm_status vlbm_set_barrier_spin_limit(uint32_t polls) {
@@ -2021,7 +2036,10 @@ vlbm_status vlbm_set_barrier_spin_limit(uint32_t polls) {
     return VLBM_OK;
 }
 
-vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps, vlbm_graph** out) {
+namespace {
+// Record n_steps of the contexts into a new graph; persistent: one persistent
+// launch per 64 contexts, else the per-stage launches of vlbm_step_batch.
+vlbm_status graph_record(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps, bool persistent, vlbm_graph** out) {
     vlbm_status st = check_batch(ctxs, n_ctx);
     if (st) return st;
     if (!out || n_steps < 1) return fail(VLBM_ERR_ARG, "bad output pointer or n_steps < 1");
@@ -2029,6 +2047,8 @@ vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps,
     if (!g) return fail(VLBM_ERR_ALLOC, "host allocation failed");
     g->ctxs.assign(ctxs, ctxs + n_ctx);
     g->steps = n_steps;
+    if (persistent)
+        for (int c0 = 0; c0 < n_ctx; c0 += MAXRUNS) g->errs.push_back(at<uint32_t>(ctxs[c0], ctxs[c0]->L.bar) + 1);
     std::vector<int64_t> before(n_ctx);
     for (int i = 0; i < n_ctx; ++i) before[i] = ctxs[i]->launches;
     // capture on a private stream (the null stream cannot be captured); the
@@ -2037,7 +2057,7 @@ vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps,
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = step_batch(ctxs, n_ctx, n_steps, cs);
+        st = persistent ? step_persistent(ctxs, n_ctx, n_steps, cs, true) : step_batch(ctxs, n_ctx, n_steps, cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         if (!st && e2 == hipSuccess) {
@@ -2056,6 +2076,27 @@ vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps,
         return st ? st : fail(VLBM_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
     }
     *out = g;
+    return VLBM_OK;
+}
+}  // namespace
+
+vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps, vlbm_graph** out) {
+    return graph_record(ctxs, n_ctx, n_steps, false, out);
+}
+
+vlbm_status vlbm_graph_create_persistent(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps, vlbm_graph** out) {
+    return graph_record(ctxs, n_ctx, n_steps, true, out);
+}
+
+vlbm_status vlbm_graph_check(vlbm_graph* g) {
+    if (!g || !g->exec) return fail(VLBM_ERR_ARG, "bad graph");
+    HIP_OK(hipStreamSynchronize(g->ctxs[0]->stream));
+    for (const uint32_t* p : g->errs) {
+        uint32_t err = 0;
+        HIP_OK(hipMemcpy(&err, p, sizeof(err), hipMemcpyDeviceToHost));
+        if (err)
+            return fail(VLBM_ERR_DEVICE, "persistent graph: a grid barrier wait gave up; the runs' state is undefined");
+    }
     return VLBM_OK;
 }
 

@@ -67,7 +67,10 @@ SIGNATURES = [
     ("vlbm_set_barrier_spin_limit", ctypes.c_int, [ctypes.c_uint32]),
     ("vlbm_graph_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
                                          ctypes.POINTER(_vp)]),
+    ("vlbm_graph_create_persistent", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int64,
+                                                   ctypes.POINTER(_vp)]),
     ("vlbm_graph_launch", ctypes.c_int, [_vp]),
+    ("vlbm_graph_check", ctypes.c_int, [_vp]),
     ("vlbm_graph_destroy", ctypes.c_int, [_vp]),
     ("vlbm_last_error", ctypes.c_char_p, []),
 ]
@@ -209,6 +212,17 @@ def vlbm_graph_create(ctxs, n: int) -> int:
     _check(load().vlbm_graph_create(_ctx_array(ctxs), len(ctxs), int(n), ctypes.byref(out)),
            "vlbm_graph_create")
     return out.value
+
+
+def vlbm_graph_create_persistent(ctxs, n: int) -> int:
+    out = _vp()
+    _check(load().vlbm_graph_create_persistent(_ctx_array(ctxs), len(ctxs), int(n), ctypes.byref(out)),
+           "vlbm_graph_create_persistent")
+    return out.value
+
+
+def vlbm_graph_check(graph):
+    _check(load().vlbm_graph_check(_vp(graph)), "vlbm_graph_check")
 
 
 def vlbm_graph_launch(graph):
@@ -422,10 +436,20 @@ class Ensemble:
         for s in self.solvers:
             s.t += n * s.dt
 
-    def capture(self, steps):
+    def capture(self, steps, persistent=False):
+        """Record ``steps`` steps as one HIP graph per launch group; with
+        ``persistent`` each graph holds one persistent launch
+        (``vlbm_graph_create_persistent``)."""
         self.release()
-        self.graphs = [vlbm_graph_create(g, steps) for g in self.groups]
+        make = vlbm_graph_create_persistent if persistent else vlbm_graph_create
+        self.graphs = [make(g, steps) for g in self.groups]
         self.graph_steps = steps
+
+    def check(self):
+        """Wait for the last replay; raise if a persistent launch in it gave up
+        at a grid barrier."""
+        for g in self.graphs:
+            vlbm_graph_check(g)
 
     def replay(self):
         for g in self.graphs:

@@ -260,3 +260,26 @@ def test_persistent_barrier_wait_gives_up_with_an_error():
         assert np.array_equal(x.populations(), y.populations())
     for s in a + b + c:
         s.close()
+
+
+def test_persistent_graph_replays_match_eager_steps():
+    # one persistent launch per replay, recorded in a HIP graph; eager work
+    # between the replays; every replay must equal eager stepping
+    from paper_2504_15574_amd import Ensemble
+    specs = [(32, 64), (48, 96), (16, 32)]
+    g = _runs("f32", specs, seed=24)
+    e = _runs("f32", specs, seed=24)
+    other = _runs("f32", [(24, 48)], seed=25)[0]
+    ens_g, ens_e = Ensemble(g), Ensemble(e)
+    ens_g.capture(4, persistent=True)
+    for rep in range(3):
+        ens_g.replay()
+        ens_g.check()
+        ens_e.step(4)
+        other.step(1)
+        _ = g[0].moments()
+        for x, y in zip(g, e):
+            assert np.array_equal(x.populations(), y.populations()), f"replay {rep}"
+    ens_g.release()
+    for s in g + e + [other]:
+        s.close()
