@@ -72,6 +72,24 @@ def test_invalid_parameters_are_rejected_on_the_host(lib):
     assert st == 1
 
 
+# the largest grids whose population buffer (Q^2 planes) stays below 4 GiB,
+# the reach of the kernels' 32-bit buffer offsets, per storage format
+MAX_GRIDS = {"f64": (4095, 8192), "f32": (8191, 8192), "f16": (16383, 8192)}
+
+
+@pytest.mark.parametrize("storage", sorted(MAX_GRIDS))
+def test_largest_grid_is_accepted_and_one_more_row_is_not(lib, storage):
+    nt, nph = MAX_GRIDS[storage]
+    b = {"f64": 8, "f32": 4, "f16": 2}[storage]
+    assert 16 * nt * nph * b < 2 ** 32 <= 16 * (nt + 1) * nph * b
+    assert B.vlbm_workspace_bytes(B.make_params(nt, nph, 1e-5, 1e-7, storage)) > 0
+    bad = B.make_params(nt + 1, nph, 1e-5, 1e-7, storage)
+    assert B.vlbm_workspace_bytes(bad) == 0
+    out = ctypes.c_void_p()
+    st = lib.vlbm_create(ctypes.byref(bad), None, ctypes.c_void_p(256), 1 << 40, ctypes.byref(out))
+    assert st == 2 and b"4 GiB" in lib.vlbm_last_error()
+
+
 def test_workspace_size_scales_with_storage(lib):
     b64 = B.vlbm_workspace_bytes(B.make_params(256, 512, 1e-3, 1e-4, "f64"))
     b32 = B.vlbm_workspace_bytes(B.make_params(256, 512, 1e-3, 1e-4, "f32"))
