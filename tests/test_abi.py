@@ -168,3 +168,14 @@ def test_fp32_quadrature_keeps_mass_and_momentum_identities(lib):
         assert mass == 1
         bound = abs(float(s4 - 3 * s22)) * abs(float(ut)) * float(u2) / 12 * 1.01
         assert abs(float(mt - ut)) <= bound + 1e-30
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; asked for more it says so and fails
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one MI355X" in (r.stdout + r.stderr) and "not supported" in (r.stdout + r.stderr)
