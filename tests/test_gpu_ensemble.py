@@ -283,3 +283,26 @@ def test_persistent_graph_replays_match_eager_steps():
     ens_g.release()
     for s in g + e + [other]:
         s.close()
+
+
+def test_graph_check_reports_a_persistent_launch_that_gave_up():
+    # The spin limit is recorded with the launch: a graph captured with a limit
+    # of 0 gives up at its first barrier on every replay (the kernel still runs
+    # to its end) and vlbm_graph_check says so; a per-stage graph checks clean.
+    from paper_2504_15574_amd import Ensemble, VlbmError, vlbm_set_barrier_spin_limit
+    runs = _runs("f32", [(32, 64), (16, 32)], seed=26)
+    ens = Ensemble(runs)
+    ens.capture(2)
+    ens.replay()
+    ens.check()
+    vlbm_set_barrier_spin_limit(0)
+    try:
+        ens.capture(2, persistent=True)
+    finally:
+        vlbm_set_barrier_spin_limit(1 << 20)
+    ens.replay()
+    with pytest.raises(VlbmError):
+        ens.check()
+    ens.release()
+    for s in runs:
+        s.close()
