@@ -262,18 +262,33 @@ template <class T> __device__ __forceinline__ T rcp_nr(T x) {
     return fma(r, fma(-x, r, T(1)), r);
 }
 
+// REST also marks the theta flux (h = sin th g); without it h is g itself
+// (phi), and the float kernels take the candidate differences from the
+// indicators' second differences: 3 (h2 - h1) + (h0 - h3) = a1 - a2,
+// 3 (h3 - h2) + (h1 - h4) = a2 - a3, 5 h2 + 2 h3 - h1 = 6 h2 + 2 D2 + D1 (one
+// instruction fewer each for A and B; FP64 keeps the direct form, whose
+// register allocation does not spill).
 template <class T, bool REST>
 __device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g2, T g3, T g4,
                                      T epsk, T wr, T c1, T c3) {
-    const T G2 = fma(T(5), h2, fma(T(2), h3, -h1));            // 6 F2
-    T A = fma(T(3), h2 - h1, h0 - h3);                          // 3 (F1 - F2)
-    T B = fma(T(3), h3 - h2, h1 - h4);                          // 6 (F3 - F2)
-    if constexpr (REST) {
-        A = fma(wr, c1, A);
-        B = fma(wr, c3, B);
+    constexpr bool DIRECT = REST || sizeof(T) == 8;
+    T G2, A, B;
+    if constexpr (DIRECT) {
+        G2 = fma(T(5), h2, fma(T(2), h3, -h1));                 // 6 F2
+        A = fma(T(3), h2 - h1, h0 - h3);                        // 3 (F1 - F2)
+        B = fma(T(3), h3 - h2, h1 - h4);                        // 6 (F3 - F2)
+        if constexpr (REST) {
+            A = fma(wr, c1, A);
+            B = fma(wr, c3, B);
+        }
     }
     const T D0 = g1 - g0, D1 = g2 - g1, D2 = g3 - g2, D3 = g4 - g3;
     const T a1 = D1 - D0, a2 = D2 - D1, a3 = D3 - D2;
+    if constexpr (!DIRECT) {
+        G2 = fma(T(6), g2, fma(T(2), D2, D1));
+        A = a1 - a2;
+        B = a2 - a3;
+    }
     const T b1 = fma(T(2), D1, a1), b2 = D1 + D2, b3 = fma(T(-2), D2, a3);
     const T e1 = fma(a1, a1, fma(T(3.0 / 13.0) * b1, b1, epsk));
     const T e2 = fma(a2, a2, fma(T(3.0 / 13.0) * b2, b2, epsk));
