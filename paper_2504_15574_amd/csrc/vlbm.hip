@@ -865,32 +865,53 @@ struct PersistArgs {
     StageArgs A;           // desc[i]: run i's stage-1 descriptor; stages 2 and 3 follow it
     int nsteps;
     uint32_t spin_limit;   // polls of one barrier wait before it gives up
-    uint32_t* bar;         // arrivals at the grid barrier, zero at the launch
+    uint32_t* bar;         // XCDs through the grid barrier, zero at the launch
     uint32_t* err;         // set to 1 when a barrier wait gave up
+    uint32_t* xbar;        // [8] arrivals per XCD, zero at the launch
+    uint32_t* xreg;        // [8] workgroups per XCD, then [8] the registration barrier's arrivals; zero at the launch
 };
+constexpr int PERSIST_WORDS = 2 + 8 + 16;
 static_assert(sizeof(PersistArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
 
-// Grid barrier: every workgroup adds one arrival (release at device scope, so
-// its stores reach the other XCDs) and polls the count with relaxed loads
-// until it reaches target; one acquire fence then makes the other workgroups'
-// stores visible to its later loads.  (An acquire on every poll would
-// invalidate the XCD's caches under the workgroups still computing.)  The
-// wait is bounded: after spin_limit polls, or once another workgroup has
-// given up, it sets err and returns, so a grid that is not co-resident still
-// ends.
-__device__ __forceinline__ void grid_barrier(const PersistArgs& P, uint32_t target) {
+// Bounded wait until *c reaches target (relaxed polls), then one acquire
+// fence: later loads see the stores released before the count.  (An acquire
+// on every poll would invalidate the XCD's caches under the workgroups still
+// computing.)  After spin_limit polls, or once another workgroup has given
+// up, it sets err and returns, so a grid that is not co-resident still ends.
+__device__ __forceinline__ void barrier_wait(const PersistArgs& P, const uint32_t* c, uint32_t target) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > P.spin_limit || __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(P.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(32);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Grid barrier number `round` (1, 2, ...), in two levels over the XCDs the
+// workgroups run on (s_xcd in LDS: the hardware XCD id, the workgroups on it
+// and the XCDs with workgroups, counted at the launch's start).  Every
+// workgroup waits until its own stores have reached its XCD's L2 (the vector
+// L1 writes through) and counts in on its XCD's counter; the last to arrive
+// writes that L2 back (a release at device scope, so the stores reach the
+// other XCDs) and counts the XCD in: one write-back per XCD and barrier
+// instead of one per workgroup, each of which would flush the whole L2 under
+// the workgroups still computing.  All then wait for every XCD.
+__device__ __forceinline__ void grid_barrier(const PersistArgs& P, uint32_t round, const uint32_t* s_xcd) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);                     // this wave's stores are in L2
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(P.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        while (__hip_atomic_load(P.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++spins > P.spin_limit || __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                __hip_atomic_store(P.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(32);
+        // (read from LDS here rather than kept in registers across the tiles)
+        const uint32_t xcc = s_xcd[0], members = s_xcd[1], groups = s_xcd[2];
+        const uint32_t old = __hip_atomic_fetch_add(P.xbar + xcc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == round * members) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(P.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        barrier_wait(P, P.bar, groups * round);
     }
     __syncthreads();
 }
@@ -916,7 +937,24 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR_WENO>())
     const int nall = A.tile_start[A.nruns];
     const int per = (nall + 7) / 8;
     const int G = (int)gridDim.x;
-    uint32_t target = 0;
+    // count the workgroups on each XCD (the hardware id; dispatch rotates the
+    // XCD a block number lands on between launches), behind a one-level
+    // barrier whose release writes back per workgroup
+    __shared__ uint32_t s_xcd[3];
+    if (threadIdx.x == 0) {
+        const uint32_t xcc = __builtin_amdgcn_s_getreg(20 | (31 << 11)) & 7u;    // XCC_ID
+        __hip_atomic_fetch_add(P.xreg + xcc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(P.xreg + 8, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        barrier_wait(P, P.xreg + 8, (uint32_t)G);
+        uint32_t groups = 0;
+        for (int i = 0; i < 8; ++i)
+            groups += __hip_atomic_load(P.xreg + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        s_xcd[0] = xcc;
+        s_xcd[1] = __hip_atomic_load(P.xreg + xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_xcd[2] = groups;
+    }
+    __syncthreads();
+    uint32_t round = 0;
     for (int step = 0; step < P.nsteps; ++step) {
         for (int stage = 0; stage < 3; ++stage) {
             for (int vb = (int)blockIdx.x; vb < 8 * per; vb += G) {
@@ -929,8 +967,7 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR_WENO>())
                 }
                 __syncthreads();                       // the tile's LDS is free again
             }
-            target += (uint32_t)G;
-            grid_barrier(P, target);
+            grid_barrier(P, ++round, s_xcd);
         }
     }
     // after the last barrier every tile has read the step counters
@@ -939,7 +976,7 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR_WENO>())
 }
 
 __global__ __launch_bounds__(64) void persist_reset_kernel(uint32_t* bar) {
-    if (threadIdx.x < 2) bar[threadIdx.x] = 0u;       // count, error flag
+    if (threadIdx.x < PERSIST_WORDS) bar[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1472,7 +1509,7 @@ Layout layout_of(const vlbm_params& p) {
     L.dout = off; off += align_up(sizeof(double) * 8);
     L.desc = off; off += align_up(sizeof(RunDesc) * 3);
     L.ctr = off; off += align_up(sizeof(uint32_t));
-    L.bar = off; off += align_up(2 * sizeof(uint32_t));   // grid barrier count, error flag
+    L.bar = off; off += align_up(PERSIST_WORDS * sizeof(uint32_t));   // persistent launch: barrier state
     L.total = off;
     return L;
 }
@@ -1771,8 +1808,10 @@ vlbm_status persist_group(vlbm_ctx* const* xs, int m, int64_t nsteps, hipStream_
     if (G < 8) return fail(VLBM_ERR_DEVICE, "no co-resident grid for the persistent stage kernel");
     P.bar = at<uint32_t>(xs[0], xs[0]->L.bar);
     P.err = P.bar + 1;
+    P.xbar = P.bar + 2;
+    P.xreg = P.bar + 10;
     P.spin_limit = g_spin_limit;
-    // one launch carries at most as many steps as the 32-bit arrival count allows
+    // one launch carries at most as many steps as the 32-bit arrival counts allow
     const int64_t chunk = std::min<int64_t>(INT32_MAX, (int64_t)(0xffffffffu / (3u * (uint32_t)G)));
     for (int64_t done = 0; done < nsteps;) {
         P.nsteps = (int)std::min(nsteps - done, chunk);
