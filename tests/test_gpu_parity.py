@@ -228,6 +228,76 @@ def test_f64_parity_full_size(nt, nph, tau, steps, maker):
     assert rel <= 1e-12
 
 
+def _degree_energy(om, th, lmax):
+    """sum_m |<om, Y_lm>|^2 per degree l (midpoint rule in theta, FFT in phi),
+    with associated Legendre functions from scipy, independent of the input
+    generator's recurrence."""
+    from scipy.special import lpmv
+    from math import factorial
+    nph = om.shape[1]
+    Z = np.fft.rfft(om, axis=1) * (2 * np.pi / nph)
+    wq = np.sin(th) * (th[1] - th[0])
+    E = np.zeros(lmax + 1)
+    for m in range(lmax + 1):
+        for l in range(max(m, 1), lmax + 1):
+            nrm = np.sqrt((2 * l + 1) / (4 * np.pi) * factorial(l - m) / factorial(l + m))
+            c = (nrm * lpmv(m, l, np.cos(th)) * wq) @ Z[:, m]
+            E[l] += (1 if m == 0 else 2) * abs(c) ** 2
+    return E
+
+
+def test_c2_full_run_decays_at_the_viscous_rates():
+    # The C2 workload run to its end: 512 x 1024, tau = 5e-4 (nu = tau), 2000
+    # steps of a rigid rotation u_phi = -1e-3 sin th plus random toroidal flow
+    # (vorticity sum_{l<=16} b_lm Y_lm, b_lm ~ N(0, 1e-8)), FP64 and FP32 store.
+    # Closed forms (Sec. IV.B; App. B): the n = 0 shear mode (rigid rotation)
+    # is undamped, and a degree-l toroidal mode decays at kappa_l =
+    # nu (l-1)(l+2) — rigid rotation only turns it (Rossby-Haurwitz), so the
+    # per-degree energy E_l (sum over m) falls as exp(-2 kappa_l t_eff).  Runs
+    # start at equilibrium, where the viscous stress builds up as
+    # 1 - exp(-t/tau) (BGK relaxation), so t_eff = t - tau (1 - exp(-t/tau)).
+    # Nonlinear transfer between degrees (amplitude 1e-4) is left out of the
+    # closed form: the measured decrements must agree with it to 1 % (FP64)
+    # or 2 % (FP32, plus its rounding noise).  FP32 vorticity within 1e-4 of
+    # FP64 after the whole run.
+    import closed_forms as cf
+    from paper_2504_15574_amd import Solver
+    nt, nph, tau, steps, lmax = 512, 1024, 5e-4, 2000, 16
+    st = W.random_vorticity_state(nt, nph, seed=0, lmax=lmax, amp=1e-4, shear=1e-3)
+    th, _ = W.grid(nt, nph)
+    G0 = cf.shear_G(0, "e", th)
+    om_end = {}
+    for storage, rel_tol, rot_tol, l1_tol in (("f64", 0.01, 1e-9, 1e-8), ("f32", 0.02, 1e-7, 1e-7)):
+        print(f"[case] C2 {storage} {nt}x{nph} tau={tau} steps={steps}", flush=True)
+        s = Solver(nt, nph, tau, storage=storage)
+        s.init_fields(*st)
+        om0 = s.vorticity()
+        s.step(steps)
+        om1 = s.vorticity()
+        _, _, up1 = s.moments(with_T=False)
+        t = steps * s.dt
+        s.close()
+        om_end[storage] = om1
+        V0 = cf.project_shear(st[2].mean(axis=1), th, G0)
+        V1 = cf.project_shear(up1.mean(axis=1), th, G0)
+        E0, E1 = _degree_energy(om0, th, lmax), _degree_energy(om1, th, lmax)
+        dec = -0.5 * np.log(E1[1:] / E0[1:])                  # degrees 1..lmax
+        t_eff = t - tau * (1.0 - np.exp(-t / tau))
+        want = np.array([cf.toroidal_kappa(l, tau) * t_eff for l in range(2, lmax + 1)])
+        rel = np.abs(dec[1:] / want - 1.0)
+        print(f"  {storage}: rigid rotation {V1 / V0 - 1:.2e}, l = 1 decrement {dec[0]:.2e}, "
+              f"l = 2..{lmax} decrement vs closed form max rel {rel.max():.2e}")
+        assert abs(V1 / V0 - 1.0) < rot_tol
+        assert abs(dec[0]) < l1_tol                           # l = 1 (tilted rotation): undamped
+        assert rel.max() < rel_tol
+        assert t > 10 * tau                                   # well past the initial layer
+    w = np.sin(th)[:, None]
+    d = om_end["f32"] - om_end["f64"]
+    err = np.sqrt((w * d * d).sum() / (w * om_end["f64"] ** 2).sum())
+    print(f"  FP32 vs FP64 vorticity after {steps} steps: {err:.2e}")
+    assert err < 1e-4
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_reduced_precision_full_size_properties(storage):
     # At the benchmark size the reduced formats stay finite, conserve the
