@@ -29,7 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles
+# VALU issue rate of FP32/FP64 arithmetic: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64
+# instruction per 4 cycles (integer adds, compares and selects issue faster, so a
+# mixed stream can exceed it)
 VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 N_THETA, N_PHI, TAU = 2048, 4096, 1e-5
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
