@@ -58,6 +58,18 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+def _fld(t, n, dtype=None):
+    """Device address of a caller's contiguous tensor holding at least n values
+    of ``dtype`` (float64 unless given); the kernels touch n values there."""
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise B.VlbmError(f"expected a contiguous {dtype} device tensor")
+    if t.numel() < n:
+        raise B.VlbmError(f"expected at least {n} values, got a tensor of {t.numel()}")
+    return t.data_ptr()
+
+
 # layer shapes: (cin, cout) padded for MFMA, (cin, cout) of the network
 LAYERS = [((8, 32), (3, 32)), ((32, 32), (32, 32)), ((32, 16), (32, 3))]
 VECTOR_MASK_IN = 0b110      # input channels 1, 2 are u_theta, u_phi
@@ -71,8 +83,10 @@ def vlbm_box_filter(n_theta_f, n_phi_f, factor, batch, rho, ut, up, rc, uc, vc, 
     """Coarse-grain FP64 device fields (torch tensors) by factor x factor boxes."""
     import torch
     s = torch.cuda.current_stream().cuda_stream if stream is None else stream
-    _ck(lib().vlbm_box_filter(n_theta_f, n_phi_f, factor, batch, _ptr(rho), _ptr(ut), _ptr(up),
-                              _ptr(rc), _ptr(uc), _ptr(vc), s), "vlbm_box_filter")
+    nf = max(batch, 0) * max(n_theta_f, 0) * max(n_phi_f, 0)
+    nc = nf // (factor * factor) if factor > 0 else 0
+    _ck(lib().vlbm_box_filter(n_theta_f, n_phi_f, factor, batch, _fld(rho, nf), _fld(ut, nf), _fld(up, nf),
+                              _fld(rc, nc), _fld(uc, nc), _fld(vc, nc), s), "vlbm_box_filter")
 
 
 class ClosureNet:
@@ -149,7 +163,8 @@ class ClosureNet:
 
     # ---- forward / backward --------------------------------------------------
     def pack_input(self, batch, rho, ut, up, s_rho, s_u):
-        _ck(lib().vlbm_clo_pack_input(self.ctx, batch, _ptr(rho), _ptr(ut), _ptr(up), float(s_rho),
+        n = max(batch, 0) * self.H * self.W
+        _ck(lib().vlbm_clo_pack_input(self.ctx, batch, _fld(rho, n), _fld(ut, n), _fld(up, n), float(s_rho),
                                       float(s_u), _ptr(self.x)), "vlbm_clo_pack_input")
 
     def forward(self, batch, x=None):
@@ -200,12 +215,16 @@ class ClosureNet:
 
     def pack_target(self, batch, a, b, o_rho, o_u, target):
         """target = (a - b) / (o_rho, o_u, o_u) from (rho, u_theta, u_phi) field triples."""
-        _ck(lib().vlbm_clo_pack_target(self.ctx, batch, *[_ptr(t) for t in a], *[_ptr(t) for t in b],
-                                       float(o_rho), float(o_u), _ptr(target)), "vlbm_clo_pack_target")
+        import torch
+        n = max(batch, 0) * self.H * self.W
+        _ck(lib().vlbm_clo_pack_target(self.ctx, batch, *[_fld(t, n) for t in a], *[_fld(t, n) for t in b],
+                                       float(o_rho), float(o_u), _fld(target, 3 * n, torch.float32)),
+            "vlbm_clo_pack_target")
 
     def unpack_output(self, batch, o_rho, o_u, drho, dut, dup):
+        n = max(batch, 0) * self.H * self.W
         _ck(lib().vlbm_clo_unpack_output(self.ctx, batch, _ptr(self.z[2]), float(o_rho), float(o_u),
-                                         _ptr(drho), _ptr(dut), _ptr(dup)), "vlbm_clo_unpack_output")
+                                         _fld(drho, n), _fld(dut, n), _fld(dup, n)), "vlbm_clo_unpack_output")
 
     def close(self):
         if getattr(self, "ctx", None):

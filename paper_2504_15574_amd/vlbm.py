@@ -234,11 +234,20 @@ def vlbm_graph_destroy(graph):
 
 
 # ---- convenience object ---------------------------------------------------------
-def _dptr(t):
+def _dptr(t, n):
+    """Device address of a contiguous float64 device tensor of exactly n values
+    (the kernels write n values there, so a shorter tensor is refused)."""
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise VlbmError("expected a contiguous float64 device tensor")
+    if t.numel() != n:
+        raise VlbmError(f"expected {n} values, got a tensor of {t.numel()}")
     return t.data_ptr()
+
+
+def _need_shape(a, shape, what):
+    if a.shape != shape:
+        raise VlbmError(f"{what}: expected shape {shape}, got {a.shape}")
 
 
 def _host(a):
@@ -289,17 +298,20 @@ class Solver:
 
     # fields already in device memory: contiguous FP64 torch tensors [n_theta, n_phi]
     def init_fields_device(self, rho, ut, up):
-        vlbm_init_fields(self.ctx, _dptr(rho), _dptr(ut), _dptr(up), None, 1)
+        n = self.n_theta * self.n_phi
+        vlbm_init_fields(self.ctx, _dptr(rho, n), _dptr(ut, n), _dptr(up, n), None, 1)
         self.t = 0.0
 
     def moments_device(self, rho, ut, up):
-        vlbm_moments(self.ctx, _dptr(rho), _dptr(ut), _dptr(up), None, 1)
+        n = self.n_theta * self.n_phi
+        vlbm_moments(self.ctx, _dptr(rho, n), _dptr(ut, n), _dptr(up, n), None, 1)
 
     def vorticity_device(self, omega):
-        vlbm_vorticity(self.ctx, _dptr(omega), 1)
+        vlbm_vorticity(self.ctx, _dptr(omega, self.n_theta * self.n_phi), 1)
 
     def correct_moments_device(self, drho, dut, dup):
-        vlbm_correct_moments(self.ctx, _dptr(drho), _dptr(dut), _dptr(dup), 1)
+        n = self.n_theta * self.n_phi
+        vlbm_correct_moments(self.ctx, _dptr(drho, n), _dptr(dut, n), _dptr(dup, n), 1)
 
     def moments(self, with_T=True):
         shape = (self.n_theta, self.n_phi)
@@ -320,14 +332,14 @@ class Solver:
 
     def set_populations(self, f):
         f, ptr = _host(f)
-        assert f.shape == (self.q * self.q, self.n_theta, self.n_phi)
+        _need_shape(f, (self.q * self.q, self.n_theta, self.n_phi), "populations")
         vlbm_set_populations(self.ctx, ptr, 0)
 
     def correct_moments(self, drho, dut, dup):
         """Add (d_rho, d_u) to the moments through the equilibrium (host fields)."""
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (drho, dut, dup)]
         for a in arrs:
-            assert a.shape == (self.n_theta, self.n_phi)
+            _need_shape(a, (self.n_theta, self.n_phi), "moment corrections")
         vlbm_correct_moments(self.ctx, arrs[0].ctypes.data, arrs[1].ctypes.data,
                              arrs[2].ctypes.data, 0)
 

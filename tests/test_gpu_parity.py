@@ -180,6 +180,34 @@ def test_diagnostics_and_vorticity_match_oracle():
     assert np.abs(om - omr).max() <= 1e-12 * np.abs(omr).max()
 
 
+def test_device_field_entry_points_refuse_short_tensors():
+    # The kernels write n_theta x n_phi values through a device pointer, so
+    # the binding refuses a tensor of another size or type before any launch.
+    import torch
+    from paper_2504_15574_amd import VlbmError
+    from paper_2504_15574_amd.closure import vlbm_box_filter
+    s = _solver(16, 32, 1e-3, 1e-4)
+    s.init_fields(*W.random_state(16, 32, seed=12, du=0.05))
+    good = [torch.empty(16, 32, dtype=torch.float64, device="cuda") for _ in range(3)]
+    s.moments_device(*good)
+    short = torch.empty(16, 31, dtype=torch.float64, device="cuda")
+    for call in (lambda: s.moments_device(good[0], short, good[2]),
+                 lambda: s.vorticity_device(short),
+                 lambda: s.init_fields_device(short, good[1], good[2]),
+                 lambda: s.correct_moments_device(good[0], good[1], short),
+                 lambda: s.moments_device(good[0].float(), good[1], good[2])):
+        with pytest.raises(VlbmError):
+            call()
+    f = torch.zeros(2 * 8 * 16, dtype=torch.float64, device="cuda")
+    c = torch.zeros(2 * 4 * 8 - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(VlbmError):
+        vlbm_box_filter(8, 16, 2, 2, f, f, f, c, c, c)
+    torch.cuda.synchronize()
+    r, a, b, _ = s.moments()
+    s.close()
+    assert np.array_equal(good[0].cpu().numpy(), r)
+
+
 def test_unstable_run_is_detected():
     # dt = 4 tau exceeds the SSP-RK3 stability limit of the stiff BGK term
     # (|dt/tau| < 2.51 on the negative real axis): the run blows up and the
