@@ -436,10 +436,17 @@ class Ensemble:
     def set_grouping(self, grouping):
         self.configure(grouping=grouping)
 
+    def _require_open(self):
+        # the launch groups and graphs hold the runs' contexts: a closed run
+        # would leave them pointing at freed state
+        if any(getattr(s, "ctx", None) is None for s in self.solvers):
+            raise VlbmError("a run of this ensemble has been closed")
+
     def step(self, n=1, persistent=False):
         """n steps of every run; ``persistent``: one cooperative launch per
         launch group carries all n steps (``vlbm_step_batch_persistent``;
         D2Q16, standard WENO-5 form; returns when done)."""
+        self._require_open()
         for g in self.groups:
             if persistent:
                 vlbm_step_batch_persistent(g, n)
@@ -452,6 +459,7 @@ class Ensemble:
         """Record ``steps`` steps as one HIP graph per launch group; with
         ``persistent`` each graph holds one persistent launch
         (``vlbm_graph_create_persistent``)."""
+        self._require_open()
         self.release()
         make = vlbm_graph_create_persistent if persistent else vlbm_graph_create
         self.graphs = [make(g, steps) for g in self.groups]
@@ -460,10 +468,12 @@ class Ensemble:
     def check(self):
         """Wait for the last replay; raise if a persistent launch in it gave up
         at a grid barrier."""
+        self._require_open()
         for g in self.graphs:
             vlbm_graph_check(g)
 
     def replay(self):
+        self._require_open()
         for g in self.graphs:
             vlbm_graph_launch(g)
         for s in self.solvers:
@@ -479,6 +489,7 @@ class Ensemble:
         advances the runs) and keep the fastest; with "by_size" and several
         grid sizes, also the combination of each size's fastest tile shape on
         its own launches.  Returns {"grouping/tile": ms per step}."""
+        self._require_open()
         import torch
 
         def timed(fn):

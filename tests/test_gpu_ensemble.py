@@ -306,3 +306,20 @@ def test_graph_check_reports_a_persistent_launch_that_gave_up():
     ens.release()
     for s in runs:
         s.close()
+
+
+def test_ensemble_refuses_work_after_a_run_is_closed():
+    # The ensemble's launch groups and graphs hold the runs' contexts; once a
+    # run is closed every call that would use them raises instead.
+    from paper_2504_15574_amd import Ensemble, VlbmError
+    runs = _runs("f32", [(32, 64), (16, 32)], seed=27)
+    ens = Ensemble(runs)
+    ens.step(1)
+    ens.capture(1)
+    runs[1].close()
+    for call in (lambda: ens.step(1), lambda: ens.replay(), lambda: ens.check(),
+                 lambda: ens.capture(1), lambda: ens.autotune(1)):
+        with pytest.raises(VlbmError):
+            call()
+    ens.release()
+    runs[0].close()
