@@ -203,7 +203,8 @@ vlbm_status vlbm_set_barrier_spin_limit(uint32_t polls);
 
 /* Record n_steps >= 1 of vlbm_step_batch(ctxs, n_ctx, .) into a HIP graph
  * (captured on a private stream; nothing runs now).  The graph refers to the
- * contexts' workspaces: destroy it before them.  Errors: VLBM_ERR_ARG,
+ * contexts (launch and check read them) and their workspaces: destroy it
+ * before either.  Errors: VLBM_ERR_ARG,
  * VLBM_ERR_DEVICE (capture or instantiation failed), VLBM_ERR_ALLOC. */
 vlbm_status vlbm_graph_create(vlbm_ctx* const* ctxs, int n_ctx, int64_t n_steps,
                               vlbm_graph** out);
