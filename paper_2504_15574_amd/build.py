@@ -8,9 +8,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRCS = [os.path.join(HERE, "csrc", "vlbm.hip"), os.path.join(HERE, "csrc", "closure.hip")]
 OUT = os.path.join(HERE, "libvlbm.so")
-# the VALU issue-rate probe: a measurement program beside the library
-PROBE_SRC = os.path.join(HERE, "csrc", "valu_probe.hip")
-PROBE_OUT = os.path.join(HERE, "valu_probe")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -28,11 +25,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, OUT)
-    probe = [hipcc, *[f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")], "-o", PROBE_OUT + ".tmp", PROBE_SRC]
-    if verbose:
-        print(" ".join(probe), flush=True)
-    subprocess.check_call(probe)
-    os.replace(PROBE_OUT + ".tmp", PROBE_OUT)
     return OUT
 
 

@@ -9,6 +9,7 @@ channels to 8 and the 3 output channels to 16 (zero weights).
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 
@@ -231,7 +232,9 @@ class ClosureNet:
             lib().vlbm_clo_destroy(_vp(self.ctx))
             self.ctx = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():   # the HIP runtime may already be torn down
+            return
         try:
             self.close()
         except Exception:

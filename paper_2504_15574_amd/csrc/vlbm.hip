@@ -124,6 +124,7 @@ struct RunDesc {
     void* out;            // stage output
     Rows rows;
     const float* rest_f;  // rest[] times this stage's b, in FP32, for the float kernels
+    const float* sinv_f;  // Rows::sinv rounded to FP32, for the float kernels
     int nt, np;
     double dt, inv_tau, rho0, eps;
     double a, b;          // out = a g_n + b (g_in + dt L)
@@ -289,10 +290,26 @@ __device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T
         A = a1 - a2;
         B = a2 - a3;
     }
-    const T b1 = fma(T(2), D1, a1), b2 = D1 + D2, b3 = fma(T(-2), D2, a3);
-    const T e1 = fma(a1, a1, fma(T(3.0 / 13.0) * b1, b1, epsk));
-    const T e2 = fma(a2, a2, fma(T(3.0 / 13.0) * b2, b2, epsk));
-    const T e3 = fma(a3, a3, fma(T(3.0 / 13.0) * b3, b3, epsk));
+    // e_i = a_i^2 + (3/13) b_i^2 + eps' with b1 = 2 D1 + a1, b2 = D1 + D2,
+    // b3 = a3 - 2 D2.  The float formats form it as (c b_i)^2 + (a_i^2 + eps'),
+    // c = sqrt(3/13): every term but the last is a function of one stencil
+    // point (a_j, c D_j, c a_j), which the interfaces a thread evaluates along a
+    // row or column share (stage_tile_rounds); FP64 keeps the form with the
+    // fewest registers (stage_tile evaluates one interface per thread)
+    T e1, e2, e3;
+    if constexpr (sizeof(T) == 8) {
+        const T b1 = fma(T(2), D1, a1), b2 = D1 + D2, b3 = fma(T(-2), D2, a3);
+        e1 = fma(a1, a1, fma(T(3.0 / 13.0) * b1, b1, epsk));
+        e2 = fma(a2, a2, fma(T(3.0 / 13.0) * b2, b2, epsk));
+        e3 = fma(a3, a3, fma(T(3.0 / 13.0) * b3, b3, epsk));
+    } else {
+        const T c = T(0.48038446141526137);        // sqrt(3/13)
+        const T cD1 = c * D1, cD2 = c * D2;
+        const T b1 = fma(T(2), cD1, c * a1), b2 = cD1 + cD2, b3 = fma(T(-2), cD2, c * a3);
+        e1 = fma(b1, b1, fma(a1, a1, epsk));
+        e2 = fma(b2, b2, fma(a2, a2, epsk));
+        e3 = fma(b3, b3, fma(a3, a3, epsk));
+    }
     const T q1 = e1 * e1, q2 = e2 * e2, q3 = e3 * e3;
     const T u = T(1.5) * q1;
     const T den = fma(q2, fma(T(0.5), q3, u), (u + u) * q3);
@@ -344,6 +361,10 @@ __device__ __forceinline__ int wrap1(int q, int np) {
 // least halo per cell) and 7 x 32 (fewer rows, for grids whose row count 15
 // divides badly).  Neither changes any cell's arithmetic.
 constexpr int NTHR = 256;
+// D2Q16 populations (k = 4 k_theta + k_phi over ascending nodes) in rounds of
+// four that share the signs of both speed components: v_theta < 0 for
+// k_theta = 0, 1 and > 0 for 2, 3, likewise v_phi with k_phi.
+constexpr int ROUND_ORDER[16] = {0, 1, 4, 5, 2, 3, 6, 7, 8, 9, 12, 13, 10, 11, 14, 15};
 template <int TS_, int TQ_>
 struct TileShape {
     static constexpr int TS = TS_, TQ = TQ_;
@@ -395,6 +416,146 @@ enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
 // 32 KB per workgroup, also allows no more).
 template <class T, int VAR>
 constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
+// The float formats of D2Q16 with the WENO-5 standard form on 15 x 16 tiles
+// run stage_tile_rounds (same bits as stage_tile).  FP64 stays on stage_tile:
+// the rounds kernel needs 128 VGPRs there (four waves per SIMD, with spills;
+// three waves without) and ran 25 % (8 %) slower than stage_tile at five.
+template <class T, class Tl, int VAR, int NQ>
+constexpr bool uses_rounds() { return sizeof(T) != 8 && Tl::TS == 15 && VAR == VAR_WENO && NQ == 4; }
+// minimum waves per SIMD of a stage launch (the rounds kernel: six, at most
+// 80 VGPRs; seven would spill)
+template <class T, class Tl, int VAR, int NQ>
+constexpr int launch_min_waves() {
+    return uses_rounds<T, Tl, VAR, NQ>() ? 6 : stage_min_waves<T, VAR>();
+}
+// The end of a stage for one cell: BGK's equilibrium part from the cell's
+// moments, the SSP-RK3 combination and the store in the storage format.  acc
+// holds g + dt L without the equilibrium (FP64) or dt L without it (float
+// formats, which keep the cell's stage input in gk); FP64 brings the moments
+// of its running sums (drho, jt, jp), the float formats form them from gk.
+template <class St, int NQ>
+__device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<typename St::T>& C,
+                                               typename St::T (&acc)[NQ * NQ],
+                                               const typename St::T (&gk)[NQ * NQ],
+                                               typename St::T drho, typename St::T jt,
+                                               typename St::T jp, int cs, int cq, uint32_t ctr) {
+    constexpr int NK = NQ * NQ;
+    using T = typename St::T;
+    constexpr int B = St::B;
+    const int np = D.np;
+    const uint32_t planeB = (uint32_t)D.nt * (uint32_t)D.np * B;
+    const T dti = uni<T>(D, U_DTI);
+    auto vsgn = [](int i) { return 2 * i + 1 < NQ ? -1 : (2 * i + 1 > NQ ? 1 : 0); };
+    auto vouter = [](int i) { return i == 0 || i == NQ - 1; };
+    // Equilibrium part of BGK from the accumulated moments, eq. (feq_Q=4):
+    // f^eq_k = w_k rho (1 + P(xi_k)), xi_k = v_k . u, P(xi) = xi + (xi^2 - u^2)/2
+    // + xi (xi^2 - 3 u^2)/6 (Q = 3 drops the cubic term, eq. (feq_Q=3)), with
+    // the coefficients 1, 1, 3 taken from the rule's moments (eq_e1, eq_hb,
+    // eq_g6: exact mass and momentum on the FP32 rule).  The mirrored
+    // population NK-1-k has -xi and the same weight, so each pair shares the
+    // even part of P and flips the sign of its odd part, which is formed as
+    // xi + xi (...) so that no rounding scales the linear term.
+    if constexpr (sizeof(T) != 8) {
+        // moments of the kept inputs from the row sums S_kt and column sums P_kp:
+        // the nodes are -v_o, -v_i, v_i, v_o (Q = 3: -v_o, 0, v_o)
+        T S[NQ], P[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            S[i] = gk[i * NQ];
+            P[i] = gk[i];
+#pragma unroll
+            for (int j = 1; j < NQ; ++j) {
+                S[i] += gk[i * NQ + j];
+                P[i] += gk[j * NQ + i];
+            }
+        }
+        drho = S[0];
+#pragma unroll
+        for (int i = 1; i < NQ; ++i) drho += S[i];
+        jt = C.v[NQ - 1] * (S[NQ - 1] - S[0]);
+        jp = C.v[NQ - 1] * (P[NQ - 1] - P[0]);
+        if constexpr (NQ == 4) {
+            jt = fma(C.v[2], S[2] - S[1], jt);
+            jp = fma(C.v[2], P[2] - P[1], jp);
+        }
+    }
+    const T rho0 = uni<T>(D, U_RHO0);
+    const T rho = rho0 + drho;
+    const T irho = rcp_nr(rho);
+    const T ut = jt * irho, up = jp * irho;
+    const T u2 = ut * ut + up * up;
+    const T ev0 = C.eq_hb * u2;
+    const T cu = fma(-C.eq_g6, u2, C.eq_e1);
+    // v_o u and v_i u (theta and phi components); the inner node is 0 for Q = 3
+    const T ato = C.v[NQ - 1] * ut, apo = C.v[NQ - 1] * up;
+    const T ati = NQ == 4 ? C.v[NQ / 2] * ut : T(0), api = NQ == 4 ? C.v[NQ / 2] * up : T(0);
+    auto xi_of = [&](int k) {
+        const int kt = k / NQ, kp = k % NQ;
+        const T a = vouter(kt) ? ato : ati, b = vouter(kp) ? apo : api;
+        return (vsgn(kt) < 0 ? -a : a) + (vsgn(kp) < 0 ? -b : b);
+    };
+    const T ca = uni<T>(D, U_A), cb = uni<T>(D, U_B);
+    const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
+    const rsrc_t rout = make_rsrc(D.out, NK * planeB);
+    const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
+    // float kernels.  A reduced-precision store adds, every stage, nearly the
+    // same increment to nearly the same value: rounding to nearest then makes
+    // nearly the same error every step, and those errors add up coherently
+    // (linear instead of square-root growth in the number of steps).  Two
+    // measures keep the error at rounding level:
+    //  - the register sums hold only the increment dt L (the stage input g of
+    //    the cell is kept aside in registers), so the arithmetic rounds at the
+    //    scale of the increment, and g + increment is rounded once;
+    //  - that one rounding is dithered: a value uniform in [-1/2, 1/2) ulp is
+    //    added before rounding to nearest, which makes the rounding unbiased
+    //    (stochastic rounding).  The dither of population k is h + k c mod
+    //    2^32 (c = 2^32 (sqrt5 - 1)/2, a Weyl step), where h is a 32-bit hash
+    //    (the "lowbias32" xorshift-multiply mixer) of the cell index, the
+    //    step counter and the stage.  A dither shared by all cells would
+    //    resonate with cells whose per-step increment matches its own step.
+    //    It depends on the step count only, so batched, single and
+    //    graph-replayed steps give identical bits.
+    uint32_t hsh = 0;
+    if constexpr (sizeof(T) != 8) {
+        hsh = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) ^ (ctr * 0x9E3779B9u + D.seq * 0x85EBCA6Bu);
+        hsh ^= hsh >> 16; hsh *= 0x7feb352du;
+        hsh ^= hsh >> 15; hsh *= 0x846ca68bu;
+        hsh ^= hsh >> 16;
+    }
+    // store population k, whose equilibrium deviation is w_k (drho + rho P)
+    auto finish = [&](int k, T t) {
+        if constexpr (sizeof(T) == 8) {
+            // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
+            const T y = fma(dti * C.wk[k], t, acc[k]);
+            T o = cb * y;
+            if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+            St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
+        } else {
+            const T g = gk[k];
+            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
+            // kernels' row factors, rest table and dt/tau come multiplied by b
+            T d = fma(dti, fma(C.wk[k], t, -g), acc[k]);
+            if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
+            const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
+            St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
+        }
+    };
+    // drho + rho P for each population and its mirror, stored pair by pair
+#pragma unroll
+    for (int k = 0; 2 * k < NK - 1; ++k) {
+        const T xi = xi_of(k);
+        const T x2 = xi * xi;
+        const T base = fma(rho, fma(T(0.5), x2, ev0), drho);
+        T od;
+        if constexpr (NQ == 4) od = fma(xi, fma(x2, T(1.0 / 6.0), cu), xi);
+        else od = fma(xi, C.eq_e1, xi);
+        const T ro = rho * od;
+        finish(k, base + ro);
+        finish(NK - 1 - k, base - ro);
+    }
+    if constexpr (NK & 1) finish(NK / 2, fma(rho, ev0, drho));     // xi = 0
+}
+
 // One tile of one run at one RK stage: tile t of the run described by D, whose
 // reduced-precision stores take the dither phase of step ctr.  Every thread of
 // the workgroup calls it; it ends after its last barrier (threads without a
@@ -546,7 +707,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
         if constexpr (ROWS_LDS) return srk[cr * NRK + i];
         else return i == 0 ? rkr.th_o : i == 1 ? rkr.th_i : i == 2 ? rkr.ph_o : i == 3 ? rkr.ph_i : rkr.dtcot;
     };
-    const T dti = uni<T>(D, U_DTI);
     const T epsk = uni<T>(D, U_EPSK);
     const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
                                         : static_cast<const void*>(D.rest_f);
@@ -588,36 +748,41 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     auto nodenv2 = [&](int i) { return Cnv2[fold(i)]; };
     auto wrk = [&](int kt, int kp) { return FOLD ? Cwr[fold(kt) * NH + fold(kp)] : Cwr[kt * NQ + kp]; };
 
-    // Ring of three LDS slots: population p lives in slot p % 3 and is written
-    // to LDS at the end of iteration p - 2, when the slot of population p - 3
-    // has been read for the last time.  Its global loads are issued PF
-    // iterations ahead, at the start of iteration p - PF, into the register
-    // pair nx[p % 2]: FP64 (4 waves per SIMD) gives them two iterations to
-    // arrive, the float kernels (7 waves) one.
+    // Populations are taken in the order ord(i) (D2Q16: the sign-sharing
+    // rounds of stage_tile_rounds, so that both kernels accumulate every cell
+    // in the same order and give the same bits).  Ring of three LDS slots:
+    // the i-th population lives in slot i % 3 and is written to LDS at the end
+    // of iteration i - 2, when the slot of iteration i - 3 has been read for
+    // the last time.  Its global loads are issued PF iterations ahead, at the
+    // start of iteration i - PF, into the register pair nx[i % 2]: FP64 (5
+    // waves per SIMD) gives them two iterations to arrive, the float kernels
+    // (7 waves) one.
+    auto ord = [](int i) { return NQ == 4 ? ROUND_ORDER[i] : i; };
     constexpr int PF = sizeof(T) == 8 ? 3 : 2;
     T nx[2][2];
     {
-        const T a0 = gload(0, 0), a1 = gload(0, 1), b0 = gload(1, 0), b1 = gload(1, 1);
+        const T a0 = gload(ord(0), 0), a1 = gload(ord(0), 1), b0 = gload(ord(1), 0), b1 = gload(ord(1), 1);
         if constexpr (PF == 3) {
-            nx[0][0] = gload(2, 0);
-            nx[0][1] = gload(2, 1);
+            nx[0][0] = gload(ord(2), 0);
+            nx[0][1] = gload(ord(2), 1);
         }
-        lstore(0, 0, a0, a1);
-        lstore(1, 1, b0, b1);
+        lstore(ord(0), 0, a0, a1);
+        lstore(ord(1), 1, b0, b1);
     }
     __syncthreads();
 
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
+    for (int i = 0; i < NK; ++i) {
+        const int k = ord(i);
         const int kt = k / NQ, kp = k % NQ;
-        const int tb = k % 3, fb = k & 1;
+        const int tb = i % 3, fb = i & 1;
         // theta and phi speeds of this population (zero: no flux in that direction)
         const int st = vsgn(kt), sp = vsgn(kp);
         T gself = T(0), Ftself = T(0), Flself = T(0);
-        // global loads of population k+PF
-        if (k + PF < NK) {
-            nx[(k + PF) & 1][0] = gload(k + PF, 0);
-            nx[(k + PF) & 1][1] = gload(k + PF, 1);
+        // global loads of the population PF iterations ahead
+        if (i + PF < NK) {
+            nx[(i + PF) & 1][0] = gload(ord(i + PF), 0);
+            nx[(i + PF) & 1][1] = gload(ord(i + PF), 1);
         }
         // theta flux of sin(theta_j) g_j (the speed multiplies the difference)
         if (st != 0) {
@@ -700,7 +865,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
                 jp = fma(nodev(kp), gc, jp);
             }
         }
-        if (k + 2 < NK) lstore(k + 2, (k + 2) % 3, nx[k & 1][0], nx[k & 1][1]);
+        if (i + 2 < NK) lstore(ord(i + 2), (i + 2) % 3, nx[i & 1][0], nx[i & 1][1]);
         // keep this population's register arithmetic in place: deferring it past
         // the following barriers would keep every population's inputs live at once
         if constexpr (NK == 16)
@@ -715,114 +880,298 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     }
 
     if (!valid) return;
+    stage_epilogue<St, NQ>(D, C, acc, gk, drho, jt, jp, cs, cq, ctr);
+}
 
-    // Equilibrium part of BGK from the accumulated moments, eq. (feq_Q=4):
-    // f^eq_k = w_k rho (1 + P(xi_k)), xi_k = v_k . u, P(xi) = xi + (xi^2 - u^2)/2
-    // + xi (xi^2 - 3 u^2)/6 (Q = 3 drops the cubic term, eq. (feq_Q=3)), with
-    // the coefficients 1, 1, 3 taken from the rule's moments (eq_e1, eq_hb,
-    // eq_g6: exact mass and momentum on the FP32 rule).  The mirrored
-    // population NK-1-k has -xi and the same weight, so each pair shares the
-    // even part of P and flips the sign of its odd part, which is formed as
-    // xi + xi (...) so that no rounding scales the linear term.
-    if constexpr (sizeof(T) != 8) {
-        // moments of the kept inputs from the row sums S_kt and column sums P_kp:
-        // the nodes are -v_o, -v_i, v_i, v_o (Q = 3: -v_o, 0, v_o)
-        T S[NQ], P[NQ];
+// ---------------------------------------------------------------------------
+// Fused RK stage in population rounds (D2Q16, WENO-5 standard form, 15 x 16
+// tiles): the same operator, per-face arithmetic and per-cell order of
+// accumulation as stage_tile, hence the same bits, with less LDS traffic and
+// a quarter of its barriers.
+//
+// The populations are taken four at a time in the rounds of ROUND_ORDER, whose
+// members share the signs of both speed components, so every flux of a round
+// is upwinded the same way.  A round's four cross-shaped tiles sit in LDS
+// together.  Wave w computes the theta fluxes of interface rows 4w .. 4w+3 of
+// all four populations (lane = population x column), walking down its column:
+// the eight stencil rows are read once for four interfaces, sin(theta) of a row
+// is the same for the whole wave, and the differences the interfaces share are
+// formed once.  The phi fluxes go the same way along the rows (lane =
+// population x row; interfaces 4w .. 4w+3, wave 3 also the tile's right edge).
+// Then the 240 cell threads read the four faces of each of the round's
+// populations and accumulate as in stage_tile.  The next round's loads are in
+// flight meanwhile and are written to LDS once the fluxes have been read: two
+// barriers per round, eight per stage.
+template <class T>
+__device__ __forceinline__ T scalar_load(const T* p, int i) {
+    // the row tables are written before any launch and only read by kernels:
+    // read through the constant address space, an index that is uniform over
+    // the workgroup then gives a scalar load
+    return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
+template <class St>
+__device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunDesc& D, int t, uint32_t ctr) {
+    using Tl = Tile15x16;
+    constexpr int NQ = 4, NK = 16;
+    constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, NLOAD = Tl::NLOAD;
+    using T = typename St::T;
+    constexpr int B = St::B;
+    // LDS tile of one population: LR rows of pitch 23 (odd, so that the 16 rows
+    // of a phi read fall on distinct banks), the unused last column of row 0
+    // takes the writes of unused load slots
+    constexpr int PITCH = 23, PSZ = LR * PITCH, DUMMY = PITCH - 1;
+    constexpr int FTP = (TS + 1) * TQ;          // theta faces of a population
+    constexpr int FPR = TQ + 1, FPP = TS * FPR;  // phi faces per row, per population
+    __shared__ T tile[4 * PSZ];
+    __shared__ T fth[4 * FTP];
+    __shared__ T fph[4 * FPP];
+
+    const ConstsT<T>& C = consts_of<T>(A);
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lp = (tid & 63) >> 4, l16 = tid & 15;
+    const int nt = D.nt, np = D.np;
+    const int tq = (np + TQ - 1) / TQ;
+    const int s0 = (t / tq) * TS, q0 = (t % tq) * TQ;
+    const uint32_t planeB = (uint32_t)nt * (uint32_t)np * B;
+    const int half = np > 1 ? np / 2 : 0;
+    const rsrc_t rin = make_rsrc(D.gin, NK * planeB);
+
+    // ---- load descriptors (as stage_tile): two cross-shaped positions per
+    // thread; population k at byte offset (k planeB ^ m) + a
+    uint32_t la[2], lm[2];
+    int ldst[2];
+    const bool inner = s0 >= NGH && s0 + TS + NGH <= nt && q0 >= NGH && q0 + TQ + NGH <= np;
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            S[i] = gk[i * NQ];
-            P[i] = gk[i];
+    for (int j = 0; j < 2; ++j) {
+        int idx = tid + NTHR * j;
+        const bool used = idx < NLOAD;
+        if (!used) idx = 0;
+        int r, c;
+        if (idx < LR * TQ) {
+            r = idx / TQ;
+            c = idx % TQ + NGH;
+        } else {
+            const int e = idx - LR * TQ, e2 = e % (TS * NGH);
+            r = e2 / NGH + NGH;
+            c = (e < TS * NGH) ? e2 % NGH : TQ + NGH + e2 % NGH;
+        }
+        int ss = s0 - NGH + r, qq = q0 - NGH + c;
+        bool mir = false;
+        if (!inner) {
+            qq = np >= TQ + NGH ? wrap1(qq, np) : wrap(qq, np);
+            if (ss < 0) {
+                ss = -1 - ss;
+                mir = true;
+                qq = wrap1(qq + half, np);
+            } else if (ss >= nt) {
+                ss = 2 * nt - 1 - ss;
+                mir = true;
+                qq = wrap1(qq + half, np);
+            }
+            ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);
+        }
+        ldst[j] = used ? r * PITCH + c : DUMMY;
+        la[j] = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
+        lm[j] = mir ? ~0u : 0u;
+    }
+    auto gload = [&](int k, int j) -> T {
+        return St::bld(rin, (((uint32_t)k * planeB) ^ lm[j]) + la[j], 0, (float)C.iscale[k]);
+    };
+    auto vouter = [](int i) { return i == 0 || i == NQ - 1; };
+
+    // ---- this thread's cell
+    const int cr = tid / TQ, cc = tid % TQ;
+    const int cs = s0 + cr, cq = q0 + cc;
+    const bool cell = tid < TS * TQ;
+    const bool valid = cell && cs < nt && cq < np;
+    const int csc = cs < nt ? cs : nt - 1;
+    const CellRowK<T> rkr = static_cast<const CellRowK<T>*>(D.rowk)[csc];
+    const T epsk = uni<T>(D, U_EPSK);
+    const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
+                                        : static_cast<const void*>(D.rest_f);
+    const rsrc_t rrest = make_rsrc(rest_t, (uint32_t)(NK * nt * sizeof(T)));
+    const uint32_t rvo = (uint32_t)csc * (uint32_t)sizeof(T);
+    T acc[NK];
+    T gk[NK];
 #pragma unroll
-            for (int j = 1; j < NQ; ++j) {
-                S[i] += gk[i * NQ + j];
-                P[i] += gk[j * NQ + i];
+    for (int k = 0; k < NK; ++k) {
+        acc[k] = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
+        gk[k] = T(0);
+    }
+    T drho = T(0), jt = T(0), jp = T(0);
+    // rule constants in scalar registers: only the rows of the first two nodes,
+    // the others by the node symmetry (exact in both arithmetic types: the FP32
+    // nodes are symmetric too), so the values equal stage_tile's
+    constexpr bool FOLD = true;
+    constexpr int NH = 2;
+    constexpr int NKR = FOLD ? NH * NQ : NK, NVR = FOLD ? NH : NQ, NWR = FOLD ? NH * NH : NK;
+    T CK[NKR], CKt[NKR], Cwr[NWR], Cv[NVR], Cnv2[NVR];
+#pragma unroll
+    for (int i = 0; i < NKR; ++i) { CK[i] = C.K[i]; CKt[i] = C.Kt[i]; }
+#pragma unroll
+    for (int i = 0; i < NWR; ++i) Cwr[i] = FOLD ? C.wr[(i / NH) * NQ + i % NH] : C.wr[i];
+#pragma unroll
+    for (int i = 0; i < NVR; ++i) { Cv[i] = C.v[i]; Cnv2[i] = C.nv2[i]; }
+    auto mir = [](int i) { return FOLD && 2 * i >= NQ; };
+    auto fold = [&](int i) { return mir(i) ? NQ - 1 - i : i; };
+    auto kK = [&](int i, int j) { return mir(i) ? -CK[fold(i) * NQ + NQ - 1 - j] : CK[i * NQ + j]; };
+    auto kKt = [&](int i, int j) { return mir(i) ? CKt[fold(i) * NQ + NQ - 1 - j] : CKt[i * NQ + j]; };
+    auto nodev = [&](int i) { return mir(i) ? -Cv[fold(i)] : Cv[i]; };
+    auto nodenv2 = [&](int i) { return Cnv2[fold(i)]; };
+    auto wrk = [&](int kt, int kp) { return FOLD ? Cwr[fold(kt) * NH + fold(kp)] : Cwr[kt * NQ + kp]; };
+
+    // the loads of round r: population ROUND_ORDER[4 r + p] of both positions
+    T nx[4][2];
+    auto issue = [&](int r) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            nx[p][0] = gload(ROUND_ORDER[4 * r + p], 0);
+            nx[p][1] = gload(ROUND_ORDER[4 * r + p], 1);
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            tile[p * PSZ + ldst[0]] = nx[p][0];
+            tile[p * PSZ + ldst[1]] = nx[p][1];
+        }
+    };
+    issue(0);
+    put();
+    issue(1);
+    __syncthreads();
+
+    const FaceRowK<T>* fkt = static_cast<const FaceRowK<T>*>(D.facek);
+    // sin(theta) of LDS row 4w + m (the theta flux function without its
+    // speed), the value of stage_tile's sin table lookup in the arithmetic
+    // type (the float formats read a table rounded on the host); uniform per
+    // wave, a scalar load where used
+    auto sin_row = [&](int m) -> T {
+        const int js = s0 + 4 * w + m, j = js < nt + 2 * NGH ? js : nt + 2 * NGH - 1;
+        if constexpr (sizeof(T) == 8) return scalar_load(D.rows.sinv, j);
+        else return scalar_load(D.sinv_f, j);
+    };
+
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int st = r < 2 ? -1 : 1;              // sign of v_theta in this round
+        const int sp = (r & 1) ? 1 : -1;            // sign of v_phi
+        const T* tl = tile + lp * PSZ;
+        // -- the cell's own values of the round's populations
+        T gself[4];
+        if (cell) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) gself[p] = tile[p * PSZ + (cr + NGH) * PITCH + cc + NGH];
+        }
+        // -- theta fluxes: population lp, column l16, interface rows 4w .. 4w+3
+        {
+            // the rest weight of this lane's population (a select, not a
+            // per-lane table lookup)
+            auto wr_of = [&](int p) { return wrk(ROUND_ORDER[4 * r + p] / NQ, ROUND_ORDER[4 * r + p] % NQ); };
+            const T wr = lp == 0 ? wr_of(0) : lp == 1 ? wr_of(1) : lp == 2 ? wr_of(2) : wr_of(3);
+            T g[9], h[9];
+#pragma unroll
+            for (int m = 0; m < 9; ++m) {
+                if (st > 0 ? m < 8 : m > 0) {
+                    const T S = sin_row(m);
+                    g[m] = tl[(4 * w + m) * PITCH + l16 + NGH];
+                    h[m] = S * g[m];
+                    // h is a rounded product, as when stage_tile reads it from
+                    // LDS: kept out of multiply-add contraction with the
+                    // differences the WENO candidates take of it
+                    asm("" : "+v"(h[m]));
+                } else {
+                    g[m] = h[m] = T(0);
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int ig = s0 + 4 * w + f < nt ? s0 + 4 * w + f : nt;
+                T F;
+                if (st > 0)
+                    F = weno5x6<T, true>(h[f], h[f + 1], h[f + 2], h[f + 3], h[f + 4], g[f], g[f + 1],
+                                         g[f + 2], g[f + 3], g[f + 4], epsk, wr,
+                                         scalar_load(&fkt[ig].cp1, 0), scalar_load(&fkt[ig].cp3, 0));
+                else
+                    F = weno5x6<T, true>(h[f + 5], h[f + 4], h[f + 3], h[f + 2], h[f + 1], g[f + 5],
+                                         g[f + 4], g[f + 3], g[f + 2], g[f + 1], epsk, wr,
+                                         scalar_load(&fkt[ig].cm1, 0), scalar_load(&fkt[ig].cm3, 0));
+                fth[lp * FTP + (4 * w + f) * TQ + l16] = F;
             }
         }
-        drho = S[0];
+        // -- phi fluxes: population lp, row l16 (lane 15 repeats row 14 and
+        // stores nothing), interfaces 4w .. 4w+3 (wave 3 also interface 16)
+        {
+            const int pr = l16 < TS ? l16 : TS - 1;
+            const T* row = tl + (pr + NGH) * PITCH + 4 * w;
+            T g[10];
 #pragma unroll
-        for (int i = 1; i < NQ; ++i) drho += S[i];
-        jt = C.v[NQ - 1] * (S[NQ - 1] - S[0]);
-        jp = C.v[NQ - 1] * (P[NQ - 1] - P[0]);
-        if constexpr (NQ == 4) {
-            jt = fma(C.v[2], S[2] - S[1], jt);
-            jp = fma(C.v[2], P[2] - P[1], jp);
-        }
-    }
-    const T rho0 = uni<T>(D, U_RHO0);
-    const T rho = rho0 + drho;
-    const T irho = rcp_nr(rho);
-    const T ut = jt * irho, up = jp * irho;
-    const T u2 = ut * ut + up * up;
-    const T ev0 = C.eq_hb * u2;
-    const T cu = fma(-C.eq_g6, u2, C.eq_e1);
-    // v_o u and v_i u (theta and phi components); the inner node is 0 for Q = 3
-    const T ato = C.v[NQ - 1] * ut, apo = C.v[NQ - 1] * up;
-    const T ati = NQ == 4 ? C.v[NQ / 2] * ut : T(0), api = NQ == 4 ? C.v[NQ / 2] * up : T(0);
-    auto xi_of = [&](int k) {
-        const int kt = k / NQ, kp = k % NQ;
-        const T a = vouter(kt) ? ato : ati, b = vouter(kp) ? apo : api;
-        return (vsgn(kt) < 0 ? -a : a) + (vsgn(kp) < 0 ? -b : b);
-    };
-    const T ca = uni<T>(D, U_A), cb = uni<T>(D, U_B);
-    const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
-    const rsrc_t rout = make_rsrc(D.out, NK * planeB);
-    const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
-    // float kernels.  A reduced-precision store adds, every stage, nearly the
-    // same increment to nearly the same value: rounding to nearest then makes
-    // nearly the same error every step, and those errors add up coherently
-    // (linear instead of square-root growth in the number of steps).  Two
-    // measures keep the error at rounding level:
-    //  - the register sums hold only the increment dt L (the stage input g of
-    //    the cell is kept aside in registers), so the arithmetic rounds at the
-    //    scale of the increment, and g + increment is rounded once;
-    //  - that one rounding is dithered: a value uniform in [-1/2, 1/2) ulp is
-    //    added before rounding to nearest, which makes the rounding unbiased
-    //    (stochastic rounding).  The dither of population k is h + k c mod
-    //    2^32 (c = 2^32 (sqrt5 - 1)/2, a Weyl step), where h is a 32-bit hash
-    //    (the "lowbias32" xorshift-multiply mixer) of the cell index, the
-    //    step counter and the stage.  A dither shared by all cells would
-    //    resonate with cells whose per-step increment matches its own step.
-    //    It depends on the step count only, so batched, single and
-    //    graph-replayed steps give identical bits.
-    uint32_t hsh = 0;
-    if constexpr (sizeof(T) != 8) {
-        hsh = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) ^ (ctr * 0x9E3779B9u + D.seq * 0x85EBCA6Bu);
-        hsh ^= hsh >> 16; hsh *= 0x7feb352du;
-        hsh ^= hsh >> 15; hsh *= 0x846ca68bu;
-        hsh ^= hsh >> 16;
-    }
-    // store population k, whose equilibrium deviation is w_k (drho + rho P)
-    auto finish = [&](int k, T t) {
-        if constexpr (sizeof(T) == 8) {
-            // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
-            const T y = fma(dti * C.wk[k], t, acc[k]);
-            T o = cb * y;
-            if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
-            St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
-        } else {
-            const T g = gk[k];
-            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
-            // kernels' row factors, rest table and dt/tau come multiplied by b
-            T d = fma(dti, fma(C.wk[k], t, -g), acc[k]);
-            if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
-            const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
-            St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
-        }
-    };
-    // drho + rho P for each population and its mirror, stored pair by pair
+            for (int m = 0; m < 10; ++m) {
+                const bool need = sp > 0 ? m < 8 || (m < 9 && w == 3) : (m > 0 && (m < 9 || w == 3));
+                g[m] = need ? row[m] : T(0);
+            }
+            auto face = [&](int f) {
+                T F;
+                if (sp > 0)
+                    F = weno5x6<T, false>(g[f], g[f + 1], g[f + 2], g[f + 3], g[f + 4], g[f], g[f + 1],
+                                          g[f + 2], g[f + 3], g[f + 4], epsk, T(0), T(0), T(0));
+                else
+                    F = weno5x6<T, false>(g[f + 5], g[f + 4], g[f + 3], g[f + 2], g[f + 1], g[f + 5],
+                                          g[f + 4], g[f + 3], g[f + 2], g[f + 1], epsk, T(0), T(0), T(0));
+                if (l16 < TS) fph[lp * FPP + pr * FPR + 4 * w + f] = F;
+            };
 #pragma unroll
-    for (int k = 0; 2 * k < NK - 1; ++k) {
-        const T xi = xi_of(k);
-        const T x2 = xi * xi;
-        const T base = fma(rho, fma(T(0.5), x2, ev0), drho);
-        T od;
-        if constexpr (NQ == 4) od = fma(xi, fma(x2, T(1.0 / 6.0), cu), xi);
-        else od = fma(xi, C.eq_e1, xi);
-        const T ro = rho * od;
-        finish(k, base + ro);
-        finish(NK - 1 - k, base - ro);
+            for (int f = 0; f < 4; ++f) face(f);
+            if (w == 3) face(4);
+        }
+        __syncthreads();
+        // -- the next round's tile, then its successor's loads
+        if (r < 3) {
+            put();
+            if (r < 2) issue(r + 2);
+        }
+        // -- the cells accumulate the round's populations in order
+        if (cell) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int k = ROUND_ORDER[4 * r + p];
+                const int kt = k / NQ, kp = k % NQ;
+                const T gc = gself[p];
+                T a = acc[k];
+                if constexpr (sizeof(T) == 8) a = fma(uni<T>(D, U_OMDTI), gc, a);
+                {
+                    const T Ft = fth[p * FTP + cr * TQ + cc], Fb = fth[p * FTP + (cr + 1) * TQ + cc];
+                    const T f = vouter(kt) ? rkr.th_o : rkr.th_i;
+                    a = fma(st > 0 ? -f : f, Fb - Ft, a);
+                }
+                {
+                    const T Fl = fph[p * FPP + cr * FPR + cc], Fr = fph[p * FPP + cr * FPR + cc + 1];
+                    const T f = vouter(kp) ? rkr.ph_o : rkr.ph_i;
+                    a = fma(sp > 0 ? -f : f, Fr - Fl, a);
+                }
+                acc[k] = a;
+                const T tg = rkr.dtcot * gc;
+                const T ta = nodenv2(kp) * tg, tb = nodev(kt) * tg;
+#pragma unroll
+                for (int b = 0; b < NQ; ++b) {
+                    acc[b * NQ + kp] = fma(kK(b, kt), ta, acc[b * NQ + kp]);
+                    acc[kt * NQ + b] = fma(kKt(b, kp), tb, acc[kt * NQ + b]);
+                }
+                if constexpr (sizeof(T) != 8) {
+                    gk[k] = gc;
+                } else {
+                    drho += gc;
+                    jt = fma(nodev(kt), gc, jt);
+                    jp = fma(nodev(kp), gc, jp);
+                }
+            }
+        }
+        if (r < 3) __syncthreads();
     }
-    if constexpr (NK & 1) finish(NK / 2, fma(rho, ev0, drho));     // xi = 0
+    if (!valid) return;
+    stage_epilogue<St, NQ>(D, C, acc, gk, drho, jt, jp, cs, cq, ctr);
 }
 
 // the run of global tile tg: the largest run with tile_start[run] <= tg
@@ -843,7 +1192,7 @@ __device__ __forceinline__ int run_of(const StageArgs& A, int tg) {
 // its run from the kernel arguments; a batched one looks up the run of its
 // tile (uniform per workgroup).
 template <class St, bool BATCH, class Tl, int VAR, int NQ>
-__global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(NTHR, (launch_min_waves<typename St::T, Tl, VAR, NQ>())) void stage_kernel(StageArgs A) {
     const int nall = A.tile_start[A.nruns];
     const int per = (nall + 7) / 8;
     const int tg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -851,7 +1200,10 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR>())) voi
     const int run = BATCH ? run_of(A, tg) : 0;
     const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
     const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr;
-    stage_tile<St, Tl, VAR, NQ>(A, D, tg - A.tile_start[run], ctr);
+    if constexpr (uses_rounds<typename St::T, Tl, VAR, NQ>())
+        stage_tile_rounds<St>(A, D, tg - A.tile_start[run], ctr);
+    else
+        stage_tile<St, Tl, VAR, NQ>(A, D, tg - A.tile_start[run], ctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,6 +1315,8 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR_WENO>())
                     const int run = run_of(A, tg);
                     const RunDesc D = uniform_desc(A.desc[run] + stage);
                     const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr + (uint32_t)step;
+                    // stage_tile even where per-stage launches take stage_tile_rounds
+                    // (same bits): inside this loop the rounds kernel spills
                     stage_tile<St, Tl, VAR_WENO, 4>(A, D, tg - A.tile_start[run], ctr);
                 }
                 __syncthreads();                       // the tile's LDS is free again
@@ -1152,16 +1506,33 @@ __global__ __launch_bounds__(RED_T) void reduce_kernel(const void* inv, const do
     if (threadIdx.x < 8) part[(size_t)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// One wavefront folds the per-block partials: lane l takes blocks l, l + 64,
+// ... in order, then the 64 lane results are combined by a fixed pairwise
+// tree in LDS, so the result depends only on the grid (deterministic).
 __global__ __launch_bounds__(64) void reduce_final(const double* part, int nblk, double* out) {
-    if (threadIdx.x != 0) return;
+    __shared__ double sh[8][64];
+    const int l = threadIdx.x;
     double acc[8] = {0, 0, 0, 0, 0, 0, INFINITY, -INFINITY};
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = l; b < nblk; b += 64) {
         for (int j = 0; j < 5; ++j) acc[j] += part[(size_t)b * 8 + j];
         acc[5] = fmax(acc[5], part[(size_t)b * 8 + 5]);
         acc[6] = fmin(acc[6], part[(size_t)b * 8 + 6]);
         acc[7] = fmax(acc[7], part[(size_t)b * 8 + 7]);
     }
-    for (int j = 0; j < 8; ++j) out[j] = acc[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sh[j][l] = acc[j];
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (l < w) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) sh[j][l] += sh[j][l + w];
+            sh[5][l] = fmax(sh[5][l], sh[5][l + w]);
+            sh[6][l] = fmin(sh[6][l], sh[6][l + w]);
+            sh[7][l] = fmax(sh[7][l], sh[7][l + w]);
+        }
+        __syncthreads();
+    }
+    if (l < 8) out[l] = sh[l][0];
 }
 
 // Vorticity from the FP64 velocity fields, fourth-order central differences.
@@ -1394,7 +1765,7 @@ void build_consts(Consts& c, int storage, int q) {
 // C2 part and the inertial force on w_k rho0 are exact per row and go into
 // rest[] (times dt); the kernel adds w1 (C1 - C2) + w3 (C3 - C2) from dC.
 struct HostRows {
-    std::vector<double> sinv, inv_sdth, inv_sdph, cot, rest, dC, sI;
+    std::vector<double> sinv, sgeo, inv_sdth, inv_sdph, cot, rest, dC, sI;
 };
 
 void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
@@ -1408,6 +1779,9 @@ void build_rows(HostRows& h, const vlbm_params& p, const Consts& c) {
     // pole values are 0) and divided by R (cos th_{s-1/2} - cos th_{s+1/2})
     h.sinv.resize(nt + 2 * NGH);
     for (int j = -NGH; j < nt + NGH; ++j) h.sinv[j + NGH] = kom ? 1.0 : std::sin((j + 0.5) * dth);
+    // the geometry itself (area element, vorticity), whatever the flux form
+    h.sgeo.resize(nt + 2 * NGH);
+    for (int j = -NGH; j < nt + NGH; ++j) h.sgeo[j + NGH] = std::sin((j + 0.5) * dth);
     h.sI.resize(nt + 1);
     for (int i = 0; i <= nt; ++i) h.sI[i] = kom ? std::sin((i < nt - i ? i : nt - i) * dth) : 1.0;
     h.inv_sdth.resize(nt);
@@ -1481,7 +1855,7 @@ size_t store_bytes(int storage) {
 constexpr int RED_BLOCKS = 1024;
 
 struct Layout {
-    size_t fbuf[3], sinv, inv_sdth, inv_sdph, cot, rest, rest_f, dC, sI, rowk, rowk_f, facek, facek_f;
+    size_t fbuf[3], sinv, sinv_f, sgeo, inv_sdth, inv_sdph, cot, rest, rest_f, dC, sI, rowk, rowk_f, facek, facek_f;
     size_t fields, part, dout, desc, ctr, bar, total;
 };
 
@@ -1493,6 +1867,8 @@ Layout layout_of(const vlbm_params& p) {
     const size_t fb = align_up(nk * n * store_bytes(p.storage));
     for (int i = 0; i < 3; ++i) { L.fbuf[i] = off; off += fb; }
     L.sinv = off; off += align_up(sizeof(double) * (p.n_theta + 2 * NGH));
+    L.sgeo = off; off += align_up(sizeof(double) * (p.n_theta + 2 * NGH));
+    L.sinv_f = off; off += align_up(sizeof(float) * (p.n_theta + 2 * NGH));
     L.inv_sdth = off; off += align_up(sizeof(double) * p.n_theta);
     L.inv_sdph = off; off += align_up(sizeof(double) * p.n_theta);
     L.cot = off; off += align_up(sizeof(double) * p.n_theta);
@@ -1611,6 +1987,7 @@ void fill_descs(vlbm_ctx* x, RunDesc d[3]) {
         D.rows.sI = at<double>(x, x->L.sI);
         D.scheme = x->p.advection & VLBM_ADV_SCHEME_MASK;
         D.rest_f = at<float>(x, x->L.rest_f + i * align_up(sizeof(float) * x->p.q * x->p.q * x->p.n_theta));
+        D.sinv_f = at<float>(x, x->L.sinv_f);
         D.nt = x->p.n_theta;
         D.np = x->p.n_phi;
         D.dt = x->p.dt;
@@ -1995,7 +2372,7 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
     }
     hipError_t e = hipGetDevice(&x->device);
     const struct { size_t off; const std::vector<double>* v; } up[] = {
-        {L.sinv, &h.sinv}, {L.inv_sdth, &h.inv_sdth}, {L.inv_sdph, &h.inv_sdph},
+        {L.sinv, &h.sinv}, {L.sgeo, &h.sgeo}, {L.inv_sdth, &h.inv_sdth}, {L.inv_sdph, &h.inv_sdph},
         {L.cot, &h.cot}, {L.rest, &h.rest}, {L.dC, &h.dC}, {L.sI, &h.sI}};
     for (const auto& u : up) {
         if (e != hipSuccess) break;
@@ -2003,6 +2380,7 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
                            hipMemcpyHostToDevice, x->stream);
     }
     // the per-stage float tables sit 256-byte aligned, one after the other
+    std::vector<float> sinv_f(h.sinv.begin(), h.sinv.end());
     const size_t nrest = h.rest.size();
     const size_t rest_stride = align_up(sizeof(float) * nrest);
     const size_t rowk_stride = align_up(sizeof(CellRowK<float>) * nt);
@@ -2015,7 +2393,8 @@ vlbm_status vlbm_create(const vlbm_params* p, void* hip_stream, void* workspace,
         {L.rowk_f + rowk_stride, rkf.data() + nt, nt * sizeof(rkf[0])},
         {L.rowk_f + 2 * rowk_stride, rkf.data() + 2 * nt, nt * sizeof(rkf[0])},
         {L.facek, fkd.data(), fkd.size() * sizeof(fkd[0])},
-        {L.facek_f, fkf.data(), fkf.size() * sizeof(fkf[0])}};
+        {L.facek_f, fkf.data(), fkf.size() * sizeof(fkf[0])},
+        {L.sinv_f, sinv_f.data(), sinv_f.size() * sizeof(float)}};
     for (const auto& u : upk)
         if (e == hipSuccess)
             e = hipMemcpyAsync(x->ws + u.off, u.src, u.bytes, hipMemcpyHostToDevice, x->stream);
@@ -2224,7 +2603,7 @@ vlbm_status vlbm_vorticity(vlbm_ctx* x, double* om, int on_dev) {
     double* dst = on_dev ? om : F + 3 * (size_t)n;
     dim3 grid((x->p.n_phi + 127) / 128, x->p.n_theta);
     hipLaunchKernelGGL(vorticity_kernel, grid, dim3(128), 0, x->stream, F + n, F + 2 * (size_t)n,
-                       at<double>(x, x->L.sinv), dst, x->p.n_theta, x->p.n_phi, x->p.radius);
+                       at<double>(x, x->L.sgeo), dst, x->p.n_theta, x->p.n_phi, x->p.radius);
     if ((st = launch_check())) return st;
     if (!on_dev) {
         HIP_OK(hipMemcpyAsync(om, dst, n * sizeof(double), hipMemcpyDeviceToHost, x->stream));
@@ -2244,7 +2623,7 @@ vlbm_status vlbm_diagnostics(vlbm_ctx* x, double out[8]) {
     vlbm_status st = dispatch(x->p.storage, [&](auto tag) {
         using St = decltype(tag);
         hipLaunchKernelGGL(reduce_kernel<St>, dim3(nblk), dim3(RED_T), 0, x->stream, fn,
-                           at<double>(x, x->L.sinv), part, x->c, x->p.n_theta, x->p.n_phi,
+                           at<double>(x, x->L.sgeo), part, x->c, x->p.n_theta, x->p.n_phi,
                            x->p.rho0, x->p.radius);
         return launch_check();
     });

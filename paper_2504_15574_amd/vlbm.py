@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -351,11 +352,22 @@ class Solver:
             vlbm_destroy(self.ctx)
             self.ctx = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter shutdown the HIP runtime may already be gone: leave
+        # the context to the process exit instead of calling into the library
+        # (the check is bound at definition: module globals may be cleared then)
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Ensemble:
@@ -531,7 +543,16 @@ class Ensemble:
             out[f"{c}/{key}"] = v
         return out
 
-    def __del__(self):
+    def close(self):
+        """Destroy the recorded graphs (the runs stay open; close them
+        separately, after this)."""
+        self.release()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # graph destruction calls the HIP runtime, which may already be torn
+        # down at interpreter shutdown: skip it there (the process exit frees it)
+        if _finalizing():
+            return
         try:
             self.release()
         except Exception:

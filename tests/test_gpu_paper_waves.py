@@ -1,0 +1,131 @@
+"""The paper's axisymmetric benchmarks on the GPU path (Sec. IV.A, IV.B).
+
+E4 (Sec. IV.B): the shear wave u_phi(0) = V0 = 1e-5 on N_theta = 512, N_phi = 1,
+dt = 1e-4, tau = 1e-3, run to t = 20, with the even-mode amplitudes V^e_n(t)
+against v^e_n exp(-kappa^e_n t) (eqs. (shear_ampl), (shear_kappaen)); the paper
+reports agreement to about 1e-7 V0.  The runs start at equilibrium, so the
+viscous stress builds up over tau and the modes decay, to first order in
+tau, as exp(-kappa (t - tau (1 - exp(-t/tau)))): a relative lag kappa_n tau
+(1e-5 .. 5.4e-5 for n = 1..3) that the closed form of the Navier-Stokes limit
+does not contain.
+
+Convergence (eq. (l2_err)): the time-integrated relative error of each mode
+against its closed form on N_theta = 16 .. 512 grids.  Sound (Sec. IV.A,
+u_theta(0) = U0 (pi - theta) theta, dt = tau = 2e-5, U0 = 1e-5; integrated to
+t = 4 rather than 20 to keep the test short): WENO-5 close to fifth order,
+U3 third, and every Komissarov variant second ("at most two").  Shear (tau =
+1e-3, dt = 1e-4, t = 20, initial layer as above): the WENO-5 order rises with
+the resolution towards the paper's four to five (measured 3.6 - 4.5 from 256
+to 512).  Measured values are printed.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_waves as PW
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    from paper_2504_15574_amd import load
+    load()
+
+
+def _t_eff(times, tau):
+    return times - tau * (1.0 - np.exp(-times / tau))
+
+
+def test_e4_shear_wave_amplitudes_match_the_closed_form():
+    tau, dt, V0, modes = 1e-3, 1e-4, 1e-5, [0, 1, 2, 3]
+    print("[case] E4 shear wave 512x1, t = 20", flush=True)
+    times, amps = PW.amplitude_series("shear", [512], tau, dt, 20.0, 200, modes, amp=V0)
+    a = amps[512]
+    raw = [np.abs(a[:, j] - PW.closed_form("shear", n, tau, times, V0)).max() / V0
+           for j, n in enumerate(modes)]
+    lag = [np.abs(a[:, j] - PW.closed_form("shear", n, tau, _t_eff(times, tau), V0)).max() / V0
+           for j, n in enumerate(modes)]
+    print("  max |V_n - closed form| / V0, n = 0..3:", " ".join(f"{x:.2e}" for x in raw))
+    print("  with the initial-layer lag:            ", " ".join(f"{x:.2e}" for x in lag))
+    # n = 0 (undamped rigid rotation, no lag): the paper's 1e-7
+    assert raw[0] < 2e-7
+    # n >= 1: the lag kappa_n tau v_n / V0 (3e-6 .. 5e-6) dominates the raw
+    # difference; with it the rest is the grid's error
+    for n in (1, 2, 3):
+        lag_bound = PW.AMPL["shear"][n][0] * (2 * n * (2 * n + 3)) * tau * tau
+        assert raw[n] < 1.2 * lag_bound + 2e-6
+        assert lag[n] < 3e-6
+    assert max(lag[:3]) < 1e-6
+
+
+def test_e4_setup_matches_the_oracle_over_a_shortened_run():
+    # the same initial state and parameters for 200 steps (t = 0.02) on both
+    # implementations, element by element
+    nt, tau, dt, n = 512, 1e-3, 1e-4, 200
+    st = W.shear_wave_const(nt, 1, 1e-5)
+    from paper_2504_15574_amd import Solver
+    s = Solver(nt, 1, tau, dt)
+    s.init_fields(*st)
+    s.step(n)
+    fg = s.populations()
+    s.close()
+    fr = oracle.step(oracle.init(*st), n, tau=tau, dt=dt)
+    d = np.abs(fg - fr).max()
+    print(f"  E4 setup, 200 steps: max |f_gpu - f_oracle| = {d:.2e} (max f {np.abs(fr).max():.3f})")
+    assert d <= 1e-12 * np.abs(fr).max()
+
+
+SOUND_NS = [16, 32, 64, 128, 256, 512]
+
+
+# orders are averaged over a window of refinements: WENO-5 and U3 over 32 -> 256
+# (from 256 to 512 WENO-5 reaches the run's error floor of ~1e-9, the kinetic
+# initial layer), the Komissarov variants over their asymptotic 128 -> 512
+@pytest.mark.parametrize("scheme,komissarov,window,lo,hi", [
+    ("weno5", False, (1, 4), 4.0, 5.6),     # fifth order (Sec. IV.A)
+    ("u3", False, (1, 4), 2.6, 3.6),        # third
+    ("u3", True, (3, 5), 1.8, 2.3),         # Komissarov form: at most two
+    ("weno5", True, (3, 5), 1.8, 2.3),
+])
+def test_sound_wave_convergence_orders(scheme, komissarov, window, lo, hi):
+    tau, dt, modes = 2e-5, 2e-5, [1, 2, 3]
+    print(f"[case] sound convergence {scheme}{' + Komissarov' if komissarov else ''}", flush=True)
+    times, amps = PW.amplitude_series("sound", SOUND_NS, tau, dt, 4.0, 100, modes,
+                                      scheme=scheme, komissarov=komissarov)
+    errs = PW.l2_errors("sound", times, amps, modes, tau)
+    o = PW.orders(errs, SOUND_NS)
+    for nt in SOUND_NS:
+        print(f"  N_theta {nt:4d}: " + " ".join(f"{e:.3e}" for e in errs[nt]))
+    print("  orders (rows: successive refinements, columns: n = 1, 2, 3):\n" + np.array2string(o, precision=2))
+    mean = o[window[0]:window[1]].mean(axis=0)
+    assert np.all(mean > lo) and np.all(mean < hi), mean
+    assert errs[SOUND_NS[-1]][0] < errs[SOUND_NS[0]][0] * 1e-2
+
+
+def test_shear_wave_convergence_order():
+    tau, dt, modes, ns = 1e-3, 1e-4, [0, 1, 2], [32, 64, 128, 256, 512]
+    print("[case] shear convergence WENO-5", flush=True)
+    times, amps = PW.amplitude_series("shear", ns, tau, dt, 20.0, 200, modes)
+    te = _t_eff(times, tau)
+    errs = {}
+    for nt, a in amps.items():
+        row = []
+        for j, n in enumerate(modes):
+            th = PW.closed_form("shear", n, tau, te, 1e-5)
+            row.append(float(np.sqrt(np.trapezoid((a[:, j] - th) ** 2, times) / np.trapezoid(th ** 2, times))))
+        errs[nt] = row
+    o = PW.orders(errs, ns)
+    for nt in ns:
+        print(f"  N_theta {nt:4d}: " + " ".join(f"{e:.3e}" for e in errs[nt]))
+    print("  orders:\n" + np.array2string(o, precision=2))
+    # the order grows with the resolution (the constant initial profile is a
+    # vortex at the poles that viscosity smooths): 3.0 -> 3.5 -> 3.8 -> 3.6-4.5
+    # over the refinements, towards the four to five the paper reports
+    assert np.all(o[-2:].mean(axis=0) > 3.5), o
+    assert np.all(o[-1] < 5.5), o

@@ -3,10 +3,11 @@
 Element-by-element comparisons on seeded inputs at sizes the oracle finishes
 in seconds, spanning several 15 x 16 tiles with ragged tails in theta and phi,
 the axisymmetric (n_phi = 1) case and the pole rows, and at the full C2 and
-benchmark grids.  FP64 storage must agree
-with the oracle to 1e-12 relative (max-abs over all populations, scaled by
-max |f|); the reduced-precision formats report their error as a number and
-are held to bounds derived from their unit round-off.
+benchmark grids.  FP64 storage must agree with the oracle to 1e-12 relative,
+both of max |f| and of the deviation scale max |f - w rho0| (plus the
+oracle's own rounding, see _assert_parity); the reduced-precision formats
+report their error as a number and are held to bounds derived from their
+unit round-off.
 """
 import os
 
@@ -44,6 +45,26 @@ def _errs(fg, fr, rho0=1.0):
     dev = fr - WK[:, None, None] * rho0
     ad = np.abs(fg - fr).max()
     return ad / np.abs(fr).max(), ad / max(np.abs(dev).max(), 1e-300)
+
+
+def _assert_parity(fg, fr, steps, rho0=1.0, what=""):
+    """FP64 parity with the oracle, element by element, in two forms:
+    - relative to the populations: max |f_gpu - f_oracle| <= 1e-12 max |f|;
+    - relative to the flow: max |f_gpu - f_oracle| <= 1e-12 max |f - w rho0|
+      plus what the oracle's own rounding accounts for.  The oracle updates f
+      itself (~0.2) and rounds it at ulp(max f) several times per stage, and
+      at small amplitudes and many steps those roundings add up (nearly the
+      same increment added to nearly the same value every stage); the GPU
+      stores f - w rho0 and rounds at that scale.  The allowance is 12 ulp(max
+      f) per step (4 per stage); the cases here use 0.1 - 0.7 of it."""
+    ad = np.abs(fg - fr).max()
+    fmax = np.abs(fr).max()
+    dev = np.abs(fr - WK[:, None, None] * rho0).max()
+    allow = 12 * steps * np.spacing(fmax)
+    print(f"  {what}max |diff| {ad:.2e}: {ad / fmax:.2e} of max |f|, {ad / dev:.2e} of the deviation "
+          f"scale; oracle rounding allowance {allow:.2e}", flush=True)
+    assert ad <= 1e-12 * fmax
+    assert ad <= 1e-12 * dev + allow
 
 
 def _run_both(state, nt, nph, tau, dt, n, storage="f64", R=1.0):
@@ -89,18 +110,14 @@ def test_f64_parity_random_states(nt, nph, seed, smooth):
     tau = 2e-3
     dt = oracle.suggest_dt(nt, nph, tau)
     fg, fr = _run_both(st, nt, nph, tau, dt, 12)
-    rel, reldev = _errs(fg, fr)
-    print(f"  max rel {rel:.2e}  (vs deviation scale {reldev:.2e})")
-    assert rel <= 1e-12
+    _assert_parity(fg, fr, 12)
 
 
 def test_f64_parity_c1_sound_wave_full():
     # C1: 32 x 64, nu = tau = 1e-3, dt = 1e-3, 500 steps, rho = 1 + 1e-3 P2(cos th)
     st = W.sound_wave_p2(32, 64)
     fg, fr = _run_both(st, 32, 64, 1e-3, 1e-3, 500)
-    rel, reldev = _errs(fg, fr)
-    print(f"  C1 max rel {rel:.2e} (deviation-relative {reldev:.2e})")
-    assert rel <= 1e-12
+    _assert_parity(fg, fr, 500, what="C1 ")
     # phi-uniform data stay bitwise phi-uniform on the GPU too
     assert np.array_equal(fg, np.repeat(fg[:, :, :1], 64, axis=2))
 
@@ -111,9 +128,7 @@ def test_f64_parity_random_vorticity_2d():
     tau = 5e-4
     dt = oracle.suggest_dt(64, 128, tau)
     fg, fr = _run_both(st, 64, 128, tau, dt, 50)
-    rel, reldev = _errs(fg, fr)
-    print(f"  C2-type max rel {rel:.2e} (deviation-relative {reldev:.2e})")
-    assert rel <= 1e-12
+    _assert_parity(fg, fr, 50, what="C2-type ")
 
 
 def test_f64_radius_and_rho0():
@@ -126,7 +141,7 @@ def test_f64_radius_and_rho0():
     fg = s.populations()
     s.close()
     fr = oracle.step(oracle.init(rho, ut, up), 10, R=2.5, tau=3e-3, dt=1e-3, threads=THREADS)
-    assert _errs(fg, fr, 1.7)[0] <= 1e-12
+    _assert_parity(fg, fr, 10, rho0=1.7)
 
 
 def test_stage_launch_count_and_determinism():
@@ -251,9 +266,7 @@ def test_f64_parity_full_size(nt, nph, tau, steps, maker):
         st = W.turbulence_state(nt, nph, seed=0, lmax=256, urms=0.05)
     dt = oracle.suggest_dt(nt, nph, tau)
     fg, fr = _run_both(st, nt, nph, tau, dt, steps)
-    rel, reldev = _errs(fg, fr)
-    print(f"  {nt}x{nph}: max rel {rel:.2e} (deviation-relative {reldev:.2e})")
-    assert rel <= 1e-12
+    _assert_parity(fg, fr, steps, what=f"{nt}x{nph} ")
 
 
 def _degree_energy(om, th, lmax):
@@ -403,6 +416,22 @@ def test_fp32_store_meets_the_benchmark_precision_gate():
          "vorticity": rel(o, o64)}
     print("  " + ", ".join(f"{k} {v:.2e}" for k, v in e.items()))
     assert all(v <= 1e-4 for v in e.values()), e
+    # The density fluctuation rho - 1 is 1.2e-9 rms at this time (the flow is
+    # nearly incompressible and the initial pressure imbalance has had a sixth
+    # of a cell's sound crossing), far below what FP32 deviations resolve: the
+    # stored populations carry ~0.02 with an ulp of 1.9e-9, and 16 dithered
+    # roundings per stage add an unbiased noise to the mass.  Its error is
+    # therefore stated, and bounded by that noise: a random walk of 3 x 1000
+    # stages of 16 roundings of at most 1/2 ulp (uniform, variance ulp^2 / 12).
+    w1 = w * np.ones_like(r)
+    w1 /= w1.sum()
+    drho = np.sqrt((w1 * (r - r64) ** 2).sum())
+    fluct = np.sqrt((w1 * (r64 - 1.0) ** 2).sum())
+    ulp = np.spacing(np.float32(0.02))
+    walk = np.sqrt(3 * 1000 * 16 / 12.0) * ulp
+    print(f"  rho - 1: FP64 rms {fluct:.2e}, FP32 rms error {drho:.2e} "
+          f"({drho / fluct:.1f} of the fluctuation; rounding-noise bound {walk:.2e})")
+    assert drho <= walk
 
 
 # the largest grids whose population buffer stays below 4 GiB (the reach of the
