@@ -168,6 +168,25 @@ double vlbm_suggest_dt(const vlbm_params* params);
  * VLBM_ERR_ARG (NULL pointer). */
 vlbm_status vlbm_quadrature_f32(float v[4], float w[16], double residual[4]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the eight
+ * diagnostics of vlbm_diagnostics (same order) of FP64 populations
+ * f [q*q][n_theta][n_phi] in device memory (full f, as vlbm_get_populations
+ * returns them), without a context or workspace.  out: device memory for 8
+ * FP64 values.  Asynchronous on hip_stream (NULL: the default stream); it
+ * neither synchronises nor allocates (no hipMalloc, no memset), so it can be
+ * recorded into a HIP graph.  Its partial sums and sin(theta) table live in a
+ * 1 MiB static device array of the library, one per device, held until the
+ * process ends and shared by every call on that device: calls that overlap in
+ * time on one device race (serialise them on one stream).  Grids up to
+ * n_theta = 122 874 rows (the table's reach) and 2^31 - 1 cells.  Unlike
+ * vlbm_diagnostics it does not report VLBM_ERR_UNSTABLE: out[4] counts the
+ * non-finite populations.  Errors: VLBM_ERR_ARG (NULL pointer, bad grid or
+ * radius, n_theta beyond the scratch), VLBM_ERR_UNSUPPORTED (q not 3 or 4),
+ * VLBM_ERR_DEVICE. */
+vlbm_status vlbm_diagnostics_static(int n_theta, int n_phi, int q, double radius, const double* f,
+                                    double* out, void* hip_stream);
+
 /* ---- ensembles (many independent runs per launch) ---- */
 
 typedef struct vlbm_graph vlbm_graph;

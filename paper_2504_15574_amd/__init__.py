@@ -10,5 +10,5 @@ from .vlbm import (  # noqa: F401
     vlbm_vorticity, vlbm_workspace_bytes, vlbm_step_batch, vlbm_graph_create, vlbm_graph_launch,
     vlbm_graph_destroy, vlbm_quadrature_f32, vlbm_correct_moments, vlbm_set_tile_shape,
     vlbm_step_batch_persistent, vlbm_set_barrier_spin_limit, vlbm_graph_create_persistent,
-    vlbm_graph_check,
+    vlbm_graph_check, vlbm_diagnostics_static,
 )

@@ -21,6 +21,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -2634,6 +2635,75 @@ vlbm_status vlbm_diagnostics(vlbm_ctx* x, double out[8]) {
     HIP_OK(hipStreamSynchronize(x->stream));
     if (out[4] > 0) return fail(VLBM_ERR_UNSTABLE, "%.0f non-finite populations", out[4]);
     return VLBM_OK;
+}
+
+// ---- diagnostics without a context or workspace -------------------------
+// The scratch of vlbm_diagnostics_static: the per-block partial sums
+// (RED_BLOCKS x 8 FP64) and the signed sin(theta) table of the grid
+// (n_theta + 6 FP64).  One copy per device, held until the process ends;
+// every call on a device shares it.
+constexpr size_t STATIC_SCRATCH_DOUBLES = (size_t)1 << 17;              // 1 MiB
+constexpr size_t STATIC_PART = 0, STATIC_SIN = (size_t)RED_BLOCKS * 8;
+constexpr int STATIC_MAX_NTHETA = (int)(STATIC_SCRATCH_DOUBLES - STATIC_SIN) - 2 * NGH;
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of this device's copy of the scratch array, looked up once
+// per device (the array's name in host code is not a device address).
+vlbm_status static_scratch(double** out) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(VLBM_ERR_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return VLBM_OK;
+}
+
+// signed sin(theta_j) for j = -3 .. nt + 2, the rows of the reduction's area
+// element (the same expression as the context's host table)
+__global__ void sin_rows_kernel(double* sinv, int nt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nt + 2 * NGH) sinv[j] = sin((j - NGH + 0.5) * (M_PI / nt));
+}
+}  // namespace
+
+vlbm_status vlbm_diagnostics_static(int n_theta, int n_phi, int q, double radius, const double* f,
+                                    double* out, void* hip_stream) {
+    if (!f || !out) return fail(VLBM_ERR_ARG, "NULL argument");
+    if (q != 3 && q != 4) return fail(VLBM_ERR_UNSUPPORTED, "q = %d: the quadratures are q = 3 and 4", q);
+    if (n_theta < 1 || n_phi < 1 || !(radius > 0) || !std::isfinite(radius))
+        return fail(VLBM_ERR_ARG, "bad grid or radius");
+    if (n_theta > STATIC_MAX_NTHETA)
+        return fail(VLBM_ERR_ARG, "n_theta = %d exceeds the static scratch (at most %d rows)", n_theta,
+                    STATIC_MAX_NTHETA);
+    if ((long long)n_theta * n_phi > (1LL << 31) - 1) return fail(VLBM_ERR_ARG, "grid too large");
+    double* sc = nullptr;
+    vlbm_status st = static_scratch(&sc);
+    if (st) return st;
+    Consts c;
+    build_consts(c, VLBM_STORE_F64, q);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int n = n_theta * n_phi;
+    int nblk = (n + RED_T - 1) / RED_T;
+    if (nblk > RED_BLOCKS) nblk = RED_BLOCKS;
+    hipLaunchKernelGGL(sin_rows_kernel, dim3((n_theta + 2 * NGH + 255) / 256), dim3(256), 0, stream,
+                       sc + STATIC_SIN, n_theta);
+    if ((st = launch_check())) return st;
+    // full populations: the deviation reference is 0
+    hipLaunchKernelGGL(reduce_kernel<StF64>, dim3(nblk), dim3(RED_T), 0, stream, f, sc + STATIC_SIN,
+                       sc + STATIC_PART, c, n_theta, n_phi, 0.0, radius);
+    if ((st = launch_check())) return st;
+    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(64), 0, stream, sc + STATIC_PART, nblk, out);
+    return launch_check();
 }
 
 // Host transfers go through the FP64 field staging area (4 planes) in chunks

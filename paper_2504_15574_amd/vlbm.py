@@ -73,6 +73,8 @@ SIGNATURES = [
     ("vlbm_graph_launch", ctypes.c_int, [_vp]),
     ("vlbm_graph_check", ctypes.c_int, [_vp]),
     ("vlbm_graph_destroy", ctypes.c_int, [_vp]),
+    ("vlbm_diagnostics_static", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_double, _vp, _vp, _vp]),
     ("vlbm_last_error", ctypes.c_char_p, []),
 ]
 
@@ -173,6 +175,14 @@ def vlbm_diagnostics(ctx, raise_unstable: bool = True) -> np.ndarray:
         return out
     _check(st, "vlbm_diagnostics")
     return out
+
+
+def vlbm_diagnostics_static(n_theta: int, n_phi: int, q: int, radius: float, f_dev: int,
+                            out_dev: int, stream: int = 0):
+    """vlbm_diagnostics_static: device pointers in, device pointer out, no
+    allocation (asynchronous on `stream`)."""
+    _check(load().vlbm_diagnostics_static(int(n_theta), int(n_phi), int(q), float(radius), _vp(f_dev),
+                                          _vp(out_dev), _vp(stream)), "vlbm_diagnostics_static")
 
 
 def vlbm_vorticity(ctx, om, on_device: int):
