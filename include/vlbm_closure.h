@@ -15,7 +15,7 @@
  *  - bf16 tensors are arrays of uint16 (IEEE bfloat16 bits); float tensors are
  *    FP32; field tensors are FP64 [batch][n_theta][n_phi].
  *  - Layer shapes: CIN in {8, 32} input channels, COUT in {16, 32} output
- *    channels (the 3 input and 3 output channels of the network are padded
+ *    channels (the 4 input and 3 output channels of the network are padded
  *    to 8 and 16 with zeros).  Weights in three layouts:
  *      master  FP32 [COUT][9 * CIN]      (k = tap * CIN + ci, tap = 3 (dy+1) + dx+1)
  *      w       bf16 [COUT][KP]           (KP = 9 * CIN rounded up to 32, zero padded)
@@ -90,9 +90,11 @@ vlbm_status vlbm_clo_pack_weights(vlbm_clo* c, int cin, int cout, const float* m
                                   void* wt);
 
 /* Network input from moment fields: x[p] = ((rho - 1) s_rho, u_theta s_u,
- * u_phi s_u, 0 x 5) as bf16 [P][8]. */
+ * u_phi s_u, (T - 1) s_T, 0 x 4) as bf16 [P][8].  T may be NULL (channel 3
+ * is then 0). */
 vlbm_status vlbm_clo_pack_input(vlbm_clo* c, int batch, const double* rho, const double* u_theta,
-                                const double* u_phi, double s_rho, double s_u, void* x);
+                                const double* u_phi, const double* T, double s_rho, double s_u,
+                                double s_T, void* x);
 
 /* Moment corrections from the network output z (FP32 [P][16]): d_rho = z0 o_rho,
  * d_u_theta = z1 o_u, d_u_phi = z2 o_u (FP64 fields). */

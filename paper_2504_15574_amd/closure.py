@@ -30,7 +30,7 @@ SIGNATURES = [
     ("vlbm_clo_loss", _i, [_vp, _i, _vp, _vp, _vp, _vp, ctypes.POINTER(_i)]),
     ("vlbm_clo_adam", _i, [_vp, _i, _vp, _vp, _vp, _vp, _i, _f, _f, _f, _f]),
     ("vlbm_clo_pack_weights", _i, [_vp, _i, _i, _vp, _vp, _vp]),
-    ("vlbm_clo_pack_input", _i, [_vp, _i, _vp, _vp, _vp, _d, _d, _vp]),
+    ("vlbm_clo_pack_input", _i, [_vp, _i, _vp, _vp, _vp, _vp, _d, _d, _d, _vp]),
     ("vlbm_clo_unpack_output", _i, [_vp, _i, _vp, _d, _d, _vp, _vp, _vp]),
     ("vlbm_clo_pack_target", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),
     ("vlbm_box_filter", _i, [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -72,8 +72,8 @@ def _fld(t, n, dtype=None):
 
 
 # layer shapes: (cin, cout) padded for MFMA, (cin, cout) of the network
-LAYERS = [((8, 32), (3, 32)), ((32, 32), (32, 32)), ((32, 16), (32, 3))]
-VECTOR_MASK_IN = 0b110      # input channels 1, 2 are u_theta, u_phi
+LAYERS = [((8, 32), (4, 32)), ((32, 32), (32, 32)), ((32, 16), (32, 3))]
+VECTOR_MASK_IN = 0b110      # input channels 1, 2 are u_theta, u_phi (0: rho - 1, 3: T - 1)
 
 
 def kpad(cin):
@@ -163,10 +163,12 @@ class ClosureNet:
                                             _ptr(self.wt[li])), "vlbm_clo_pack_weights")
 
     # ---- forward / backward --------------------------------------------------
-    def pack_input(self, batch, rho, ut, up, s_rho, s_u):
+    def pack_input(self, batch, rho, ut, up, s_rho, s_u, T=None, s_T=0.0):
+        """Input channels (rho - 1) s_rho, u s_u, (T - 1) s_T (0 without T)."""
         n = max(batch, 0) * self.H * self.W
-        _ck(lib().vlbm_clo_pack_input(self.ctx, batch, _fld(rho, n), _fld(ut, n), _fld(up, n), float(s_rho),
-                                      float(s_u), _ptr(self.x)), "vlbm_clo_pack_input")
+        _ck(lib().vlbm_clo_pack_input(self.ctx, batch, _fld(rho, n), _fld(ut, n), _fld(up, n),
+                                      _fld(T, n) if T is not None else None, float(s_rho), float(s_u),
+                                      float(s_T), _ptr(self.x)), "vlbm_clo_pack_input")
 
     def forward(self, batch, x=None):
         """Run the three layers on self.x (or the given bf16 [P][8] tensor);
@@ -241,9 +243,9 @@ class ClosureNet:
             pass
 
 
-def init_params(rng, hidden=32):
+def init_params(rng, hidden=32, cin=4):
     """He-normal weights (the last layer scaled by 0.1), zero biases."""
-    shapes = [(hidden, 9, 3), (hidden, 9, hidden), (3, 9, hidden)]
+    shapes = [(hidden, 9, cin), (hidden, 9, hidden), (3, 9, hidden)]
     ps = []
     for i, s in enumerate(shapes):
         std = np.sqrt(2.0 / (9 * s[2])) * (1.0 if i < 2 else 0.1)

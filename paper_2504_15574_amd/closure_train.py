@@ -10,10 +10,10 @@ Setting (all runs on one device, every step of every run in the library):
            rms |u| = urms, nu = tau (T0 = 1)
   filter   box averages of f x f fine cells (area and momentum weighted)
 
-The closure acts once per interval of k coarse steps: the coarse run advances k
-steps, the network maps its moments (rho - 1, u) to a correction (d_rho, d_u),
-and the correction enters the populations through the equilibrium
-(vlbm_correct_moments).  Training pairs come from the fine runs: the input is
+The closure acts once per interval of k coarse steps (k = 1: every step): the
+coarse run advances k steps, the network maps its moments (rho - 1, u, T - 1)
+to a correction (d_rho, d_u), and the correction enters the populations
+through the equilibrium (vlbm_correct_moments).  Training pairs come from the fine runs: the input is
 the coarse run's state one interval after it started from the filtered fine
 state X_n, the target the filtered fine state X_{n+1} minus that prediction.
 
@@ -30,7 +30,7 @@ import json
 import math
 import sys
 import time
-from dataclasses import asdict, dataclass, field
+from dataclasses import asdict, dataclass, field, replace
 
 import numpy as np
 
@@ -95,7 +95,7 @@ class _Events:
         self.ms += self.e0.elapsed_time(self.e1)
 
 
-def fine_filtered(cfg, seeds):
+def fine_filtered(cfg, seeds, storage="f32"):
     """Filtered fine states X[n] (n = 0..intervals) for the seeds: three FP64
     device tensors per interval, [len(seeds)][n_theta_c][n_phi_c] each.  Also
     returns the fine cost in ms of device time per run per unit simulated time."""
@@ -111,7 +111,7 @@ def fine_filtered(cfg, seeds):
     for i0 in range(0, N, cfg.batch):
         chunk = seeds[i0:i0 + cfg.batch]
         B = len(chunk)
-        sols = [Solver(Hf, Wf, cfg.tau, dt_f, storage="f32") for _ in chunk]
+        sols = [Solver(Hf, Wf, cfg.tau, dt_f, storage=storage) for _ in chunk]
         for s, sd in zip(sols, chunk):
             s.init_fields(*W.turbulence_state(Hf, Wf, seed=sd, lmax=cfg.lmax, urms=cfg.urms)[:3])
         ens = Ensemble(sols)
@@ -138,7 +138,7 @@ class CoarsePool:
         self.sols = [Solver(cfg.n_theta_c, cfg.n_phi_c, cfg.tau, cfg.dt_c, storage="f32")
                      for _ in range(B)]
         self.ens = Ensemble(self.sols)
-        self.mom = _fields(B, cfg.n_theta_c, cfg.n_phi_c)
+        self.mom = _fields(B, cfg.n_theta_c, cfg.n_phi_c) + _fields(B, cfg.n_theta_c, cfg.n_phi_c)[:1]
         self.corr = _fields(B, cfg.n_theta_c, cfg.n_phi_c)
 
     def load(self, X, idx=None):
@@ -147,9 +147,10 @@ class CoarsePool:
             s.init_fields_device(X[0][j], X[1][j], X[2][j])
 
     def moments(self, out=None):
+        """rho, u_theta, u_phi and T of every run."""
         out = self.mom if out is None else out
         for b, s in enumerate(self.sols):
-            s.moments_device(out[0][b], out[1][b], out[2][b])
+            s.moments_device(out[0][b], out[1][b], out[2][b], out[3][b])
         return out
 
     def interval(self, net=None, stats=None):
@@ -157,7 +158,7 @@ class CoarsePool:
         self.ens.step(self.cfg.k)
         if net is not None:
             m = self.moments()
-            net.pack_input(self.B, *m, stats["s_rho"], stats["s_u"])
+            net.pack_input(self.B, *m[:3], stats["s_rho"], stats["s_u"], T=m[3], s_T=stats["s_T"])
             net.forward(self.B)
             net.unpack_output(self.B, stats["o_rho"], stats["o_u"], *self.corr)
             for b, s in enumerate(self.sols):
@@ -181,7 +182,7 @@ def build_dataset(cfg, X):
         T.append(X[n + 1])
     pool.close()
     cat = lambda L, c: torch.cat([x[c] for x in L], 0).contiguous()
-    return [cat(Y, c) for c in range(3)], [cat(T, c) for c in range(3)]
+    return [cat(Y, c) for c in range(4)], [cat(T, c) for c in range(3)]
 
 
 def fit(cfg, Y, T, log=None):
@@ -190,22 +191,25 @@ def fit(cfg, Y, T, log=None):
     from .closure import ClosureNet
     M = Y[0].shape[0]
     d = [T[c] - Y[c] for c in range(3)]
+    sT = float((Y[3] - 1.0).std())
     stats = {"s_rho": 1.0 / float((Y[0] - 1.0).std()), "s_u": 1.0 / float(torch.cat([Y[1], Y[2]]).std()),
+             "s_T": 1.0 / sT if sT > 0 else 0.0,
              "o_rho": float(d[0].std()), "o_u": float(torch.cat([d[1], d[2]]).std())}
     mb = min(cfg.minibatch, M)
     net = ClosureNet(cfg.n_theta_c, cfg.n_phi_c, mb, seed=cfg.seed)
     target = torch.zeros(mb * cfg.n_theta_c * cfg.n_phi_c * 3, dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(cfg.seed)
-    bufY = _fields(mb, cfg.n_theta_c, cfg.n_phi_c)
+    bufY = _fields(mb, cfg.n_theta_c, cfg.n_phi_c) + _fields(mb, cfg.n_theta_c, cfg.n_phi_c)[:1]
     bufT = _fields(mb, cfg.n_theta_c, cfg.n_phi_c)
     hist = []
     for it in range(cfg.iters):
         idx = torch.from_numpy(rng.choice(M, size=mb, replace=False)).cuda()
-        for c in range(3):
+        for c in range(4):
             torch.index_select(Y[c], 0, idx, out=bufY[c])
+        for c in range(3):
             torch.index_select(T[c], 0, idx, out=bufT[c])
-        net.pack_input(mb, *bufY, stats["s_rho"], stats["s_u"])
-        net.pack_target(mb, bufT, bufY, stats["o_rho"], stats["o_u"], target)
+        net.pack_input(mb, *bufY[:3], stats["s_rho"], stats["s_u"], T=bufY[3], s_T=stats["s_T"])
+        net.pack_target(mb, bufT, bufY[:3], stats["o_rho"], stats["o_u"], target)
         net.forward(mb)
         lr = cfg.lr * (0.1 ** (it / max(cfg.iters - 1, 1)))      # exponential decay to lr / 10
         hist.append(net.loss(mb, target))
@@ -288,24 +292,70 @@ def evaluate(cfg, net, stats, X, fine_ms):
     return out
 
 
-def run(cfg, log=print):
+def _filtered_difference(cfg, A, Bf):
+    """Mean over runs of the relative L2 of the vorticity of coarse fields A
+    against Bf (three FP64 device tensors each, [runs][n_theta_c][n_phi_c])."""
+    import torch
+    from .vlbm import Solver
+    H, Wd = cfg.n_theta_c, cfg.n_phi_c
+    w = np.sin((np.arange(H) + 0.5) * np.pi / H)[:, None]
+    diag = Solver(H, Wd, cfg.tau, cfg.dt_c, storage="f64")
+    om = torch.zeros((H, Wd), dtype=torch.float64, device="cuda")
+    errs = []
+    for b in range(A[0].shape[0]):
+        o = []
+        for F in (A, Bf):
+            diag.init_fields_device(F[0][b].contiguous(), F[1][b].contiguous(), F[2][b].contiguous())
+            diag.vorticity_device(om)
+            o.append(om.cpu().numpy().copy())
+        errs.append(_rel(o[0], o[1], w))
+    diag.close()
+    return float(np.mean(errs))
+
+
+def run(cfg, log=print, ks=None):
+    """Fine data, training and evaluation for every closure interval k in ks
+    (default: cfg.k) over the same simulated time cfg.intervals * cfg.k coarse
+    steps.  The fine runs are made once, filtered at the finest interval;
+    returns {k: result} (or the result of cfg.k alone when ks is None)."""
+    single = ks is None
+    ks = [cfg.k] if single else list(ks)
+    steps = cfg.intervals * cfg.k
+    assert all(steps % k == 0 for k in ks), "every interval must divide the run"
+    kmin = math.gcd(*ks) if len(ks) > 1 else ks[0]
     t0 = time.time()
     log(f"fine substeps per coarse step: {fine_substeps(cfg)}")
-    Xtr, fine_ms = fine_filtered(cfg, cfg.train_seeds)
-    log(f"training data: {len(cfg.train_seeds)} fine runs, {time.time() - t0:.1f} s")
-    Y, T = build_dataset(cfg, Xtr)
-    net, stats, hist = fit(cfg, Y, T, log)
-    log(f"trained: {time.time() - t0:.1f} s")
-    Xev, fine_ms_ev = fine_filtered(cfg, cfg.eval_seeds)
-    res = evaluate(cfg, net, stats, Xev, fine_ms_ev)
-    res["config"] = {k: v for k, v in asdict(cfg).items() if k not in ("train_seeds", "eval_seeds")}
-    res["config"].update(n_train=len(cfg.train_seeds), n_eval=len(cfg.eval_seeds),
-                         fine_substeps=fine_substeps(cfg))
-    res["loss_first_last"] = [hist[0], hist[-1]]
-    res["stats"] = stats
-    res["wall_s"] = time.time() - t0
-    net.close()
-    return res
+    base = replace(cfg, k=kmin, intervals=steps // kmin)
+    Xtr_all, fine_ms = fine_filtered(base, cfg.train_seeds)
+    Xev_all, fine_ms_ev = fine_filtered(base, cfg.eval_seeds)
+    log(f"fine data: {len(cfg.train_seeds)} + {len(cfg.eval_seeds)} runs, {time.time() - t0:.1f} s")
+    # the training and reference data come from FP32-store fine runs: their
+    # filtered end state against FP64-store runs of the first two held-out seeds
+    seeds2 = cfg.eval_seeds[:2]
+    X64, _ = fine_filtered(replace(cfg, intervals=1, k=steps), seeds2, storage="f64")
+    fine_fp32_err = _filtered_difference(cfg, [x[:2] for x in Xev_all[-1]], X64[-1])
+    log(f"fine runs, FP32 vs FP64 store, filtered end state: vorticity rel L2 {fine_fp32_err:.2e}")
+    out = {}
+    for k in ks:
+        t1 = time.time()
+        ck = replace(cfg, k=k, intervals=steps // k)
+        sub = k // kmin
+        Xtr, Xev = Xtr_all[::sub], Xev_all[::sub]
+        Y, T = build_dataset(ck, Xtr)
+        net, stats, hist = fit(ck, Y, T, log)
+        del Y, T
+        log(f"k = {k}: trained in {time.time() - t1:.1f} s")
+        res = evaluate(ck, net, stats, Xev, fine_ms_ev)
+        res["config"] = {a: v for a, v in asdict(ck).items() if a not in ("train_seeds", "eval_seeds")}
+        res["config"].update(n_train=len(cfg.train_seeds), n_eval=len(cfg.eval_seeds),
+                             fine_substeps=fine_substeps(cfg))
+        res["loss_first_last"] = [hist[0], hist[-1]]
+        res["fine_fp32_vs_fp64_vorticity_rel_l2"] = fine_fp32_err
+        res["stats"] = stats
+        res["wall_s"] = time.time() - t1
+        net.close()
+        out[k] = res
+    return out[ks[0]] if single else out
 
 
 def main(argv=None):

@@ -328,13 +328,15 @@ __global__ void pack_w_kernel(const float* __restrict__ master, int cin, int cou
 
 __global__ void pack_input_kernel(int P, const double* __restrict__ rho,
                                   const double* __restrict__ ut, const double* __restrict__ up,
-                                  double s_rho, double s_u, uint16_t* __restrict__ x) {
+                                  const double* __restrict__ T, double s_rho, double s_u,
+                                  double s_T, uint16_t* __restrict__ x) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
     v[0] = to_bf16((float)((rho[p] - 1.0) * s_rho));
     v[1] = to_bf16((float)(ut[p] * s_u));
     v[2] = to_bf16((float)(up[p] * s_u));
+    if (T) v[3] = to_bf16((float)((T[p] - 1.0) * s_T));
     *reinterpret_cast<u16x8*>(x + (size_t)p * 8) = v;
 }
 
@@ -620,12 +622,13 @@ vlbm_status vlbm_clo_pack_weights(vlbm_clo* c, int cin, int cout, const float* m
 }
 
 vlbm_status vlbm_clo_pack_input(vlbm_clo* c, int batch, const double* rho, const double* ut,
-                                const double* up, double s_rho, double s_u, void* x) {
+                                const double* up, const double* T, double s_rho, double s_u,
+                                double s_T, void* x) {
     if (vlbm_status st = check_batch(c, batch)) return st;
     if (!rho || !ut || !up || !x) return err(VLBM_ERR_ARG, "NULL tensor");
     const int P = c->H * c->W * batch;
     hipLaunchKernelGGL(pack_input_kernel, dim3((P + 255) / 256), dim3(256), 0, c->stream, P, rho,
-                       ut, up, s_rho, s_u, static_cast<uint16_t*>(x));
+                       ut, up, T, s_rho, s_u, s_T, static_cast<uint16_t*>(x));
     return launched();
 }
 

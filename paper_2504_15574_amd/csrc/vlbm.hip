@@ -291,26 +291,10 @@ __device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T
         A = a1 - a2;
         B = a2 - a3;
     }
-    // e_i = a_i^2 + (3/13) b_i^2 + eps' with b1 = 2 D1 + a1, b2 = D1 + D2,
-    // b3 = a3 - 2 D2.  The float formats form it as (c b_i)^2 + (a_i^2 + eps'),
-    // c = sqrt(3/13): every term but the last is a function of one stencil
-    // point (a_j, c D_j, c a_j), which the interfaces a thread evaluates along a
-    // row or column share (stage_tile_rounds); FP64 keeps the form with the
-    // fewest registers (stage_tile evaluates one interface per thread)
-    T e1, e2, e3;
-    if constexpr (sizeof(T) == 8) {
-        const T b1 = fma(T(2), D1, a1), b2 = D1 + D2, b3 = fma(T(-2), D2, a3);
-        e1 = fma(a1, a1, fma(T(3.0 / 13.0) * b1, b1, epsk));
-        e2 = fma(a2, a2, fma(T(3.0 / 13.0) * b2, b2, epsk));
-        e3 = fma(a3, a3, fma(T(3.0 / 13.0) * b3, b3, epsk));
-    } else {
-        const T c = T(0.48038446141526137);        // sqrt(3/13)
-        const T cD1 = c * D1, cD2 = c * D2;
-        const T b1 = fma(T(2), cD1, c * a1), b2 = cD1 + cD2, b3 = fma(T(-2), cD2, c * a3);
-        e1 = fma(b1, b1, fma(a1, a1, epsk));
-        e2 = fma(b2, b2, fma(a2, a2, epsk));
-        e3 = fma(b3, b3, fma(a3, a3, epsk));
-    }
+    const T b1 = fma(T(2), D1, a1), b2 = D1 + D2, b3 = fma(T(-2), D2, a3);
+    const T e1 = fma(a1, a1, fma(T(3.0 / 13.0) * b1, b1, epsk));
+    const T e2 = fma(a2, a2, fma(T(3.0 / 13.0) * b2, b2, epsk));
+    const T e3 = fma(a3, a3, fma(T(3.0 / 13.0) * b3, b3, epsk));
     const T q1 = e1 * e1, q2 = e2 * e2, q3 = e3 * e3;
     const T u = T(1.5) * q1;
     const T den = fma(q2, fma(T(0.5), q3, u), (u + u) * q3);

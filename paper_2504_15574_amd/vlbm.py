@@ -313,9 +313,10 @@ class Solver:
         vlbm_init_fields(self.ctx, _dptr(rho, n), _dptr(ut, n), _dptr(up, n), None, 1)
         self.t = 0.0
 
-    def moments_device(self, rho, ut, up):
+    def moments_device(self, rho, ut, up, T=None):
         n = self.n_theta * self.n_phi
-        vlbm_moments(self.ctx, _dptr(rho, n), _dptr(ut, n), _dptr(up, n), None, 1)
+        vlbm_moments(self.ctx, _dptr(rho, n), _dptr(ut, n), _dptr(up, n),
+                     _dptr(T, n) if T is not None else None, 1)
 
     def vorticity_device(self, omega):
         vlbm_vorticity(self.ctx, _dptr(omega, self.n_theta * self.n_phi), 1)

@@ -10,6 +10,9 @@ import pytest
 
 import oracle
 from oracle import closure_oracle as CO
+from paper_2504_15574_amd.closure import LAYERS
+
+CIN = LAYERS[0][1][0]      # the network's input channels (rho - 1, u_theta, u_phi, T - 1)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,11 +32,11 @@ def _setup(H, W, Bt, seed):
     from paper_2504_15574_amd.closure import ClosureNet, f64_to_bf16_bits
     rng = np.random.default_rng(seed)
     net = ClosureNet(H, W, Bt, seed=seed)
-    params = CO.init_params(rng)
+    params = CO.init_params(rng, cin=CIN)
     params = [p + 0.05 * rng.normal(size=p.shape) for p in params]
     net.set_params(params)
     x = np.zeros((Bt, H, W, 8))
-    x[..., :3] = rng.normal(size=(Bt, H, W, 3))
+    x[..., :CIN] = rng.normal(size=(Bt, H, W, CIN))
     xb = torch.from_numpy(f64_to_bf16_bits(x).reshape(-1)).cuda()
     net.x[: xb.numel()].copy_(xb)
     return net, rng
@@ -59,7 +62,7 @@ def test_each_convolution_matches_the_oracle(H, W, Bt, seed):
     torch.cuda.synchronize()
     nbr, cross = CO.neighbours(H, W)
     pb = net.bf16_params()
-    x = _b16(net.x, (Bt, H, W, 8))[..., :3]
+    x = _b16(net.x, (Bt, H, W, 8))[..., :CIN]
     ins = [x, _b16(net.a[0], (Bt, H, W, 32)), _b16(net.a[1], (Bt, H, W, 32))]
     for li, co in enumerate((32, 32, 16)):
         z = _f32(net.z[li], (Bt, H, W, co))
@@ -94,7 +97,7 @@ def test_loss_and_each_gradient_match_the_oracle(H, W, Bt, seed):
     dz3 = _b16(net.dz[2], (Bt, H, W, 16))
     assert np.abs(dz3[..., :3] - gref).max() <= 4e-3 * np.abs(gref).max()
     assert np.all(dz3[..., 3:] == 0)
-    ins = [_b16(net.x, (Bt, H, W, 8))[..., :3], _b16(net.a[0], (Bt, H, W, 32)),
+    ins = [_b16(net.x, (Bt, H, W, 8))[..., :CIN], _b16(net.a[0], (Bt, H, W, 32)),
            _b16(net.a[1], (Bt, H, W, 32))]
     dzs = [_b16(net.dz[0], (Bt, H, W, 32)), _b16(net.dz[1], (Bt, H, W, 32)), dz3[..., :3]]
     zs = [_f32(net.z[0], (Bt, H, W, 32)), _f32(net.z[1], (Bt, H, W, 32))]
@@ -125,12 +128,11 @@ def test_network_gradient_matches_the_oracle_end_to_end():
     torch.cuda.synchronize()
     nbr, cross = CO.neighbours(H, W)
     pb = net.bf16_params()
-    x = _b16(net.x, (Bt, H, W, 8))[..., :3]
+    x = _b16(net.x, (Bt, H, W, 8))[..., :CIN]
     z, cache = CO.net_forward(pb, x, nbr, cross)
     _, dz = CO.loss_and_grad(z, tgt, H)
     grads = CO.net_backward(pb, cache, dz, nbr, cross)
-    for li, ((ci, co), (rci, rco)) in enumerate((((8, 32), (3, 32)), ((32, 32), (32, 32)),
-                                                 ((32, 16), (32, 3)))):
+    for li, ((ci, co), (rci, rco)) in enumerate(LAYERS):
         gw = net.gw[li].cpu().numpy().reshape(co, 9, ci)[:rco, :, :rci]
         gb = net.gb[li].cpu().numpy()[:rco]
         rw = np.linalg.norm(gw - grads[2 * li]) / np.linalg.norm(grads[2 * li])
@@ -207,11 +209,11 @@ def test_training_reduces_the_loss():
     net, rng = _setup(H, W, Bt, 9)
     from paper_2504_15574_amd.closure import f64_to_bf16_bits
     nbr, cross = CO.neighbours(H, W)
-    teacher = CO.init_params(np.random.default_rng(123), hidden=8)
+    teacher = CO.init_params(np.random.default_rng(123), hidden=8, cin=CIN)
     x = np.zeros((Bt, H, W, 8))
-    x[..., :3] = rng.normal(size=(Bt, H, W, 3))
+    x[..., :CIN] = rng.normal(size=(Bt, H, W, CIN))
     net.x[: x.size].copy_(torch.from_numpy(f64_to_bf16_bits(x).reshape(-1)).cuda())
-    tgt, _ = CO.net_forward(teacher, x[..., :3], nbr, cross)
+    tgt, _ = CO.net_forward(teacher, x[..., :CIN], nbr, cross)
     tgt = tgt / np.abs(tgt).max()
     tg = torch.from_numpy(tgt.astype(np.float32).reshape(-1)).cuda()
     losses = []
