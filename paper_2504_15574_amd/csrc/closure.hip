@@ -187,9 +187,11 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient: block (chunk, tap) stages 256 pixels of dZ and of the
-// tap-gathered input in LDS and accumulates their product over the pixels;
-// a second kernel sums the chunks in a fixed order.
+// weight gradient: block (chunk, tap) covers WSUB x WCHUNK pixels; for each
+// WCHUNK of them it stages dZ and the tap-gathered input in LDS and the matrix
+// cores accumulate their product over the pixels in registers.  A second
+// kernel sums the chunks' partials in a fixed order (deterministic).
+constexpr int WSUB = 4;                 // WCHUNK slices per weight-gradient block
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void conv_bwd_w_kernel(
     const uint16_t* __restrict__ x, const uint16_t* __restrict__ dz, const int* __restrict__ nbr,
@@ -200,8 +202,15 @@ __global__ __launch_bounds__(256) void conv_bwd_w_kernel(
     __shared__ uint16_t xs[WCHUNK * XS];
     __shared__ uint16_t ds[WCHUNK * DS];
     const int chunk = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
-    {
-        const int p = chunk * WCHUNK + tid;
+    constexpr int MB = COUT / 16, NBc = CI16 / 16;
+    constexpr int NPAIR = (MB * NBc + WAVES - 1) / WAVES;    // (mb, nb) pairs per wave
+    const int wv = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    f32x4 acc[NPAIR];
+#pragma unroll
+    for (int j = 0; j < NPAIR; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float sb = 0.f;                            // bias gradient (tap 4, threads < COUT)
+    for (int sub = 0; sub < WSUB; ++sub) {
+        const int p = (chunk * WSUB + sub) * WCHUNK + tid;
         if (p < P) {
             const int s = p / HW, hw = p - s * HW;
             const int q = s * HW + nbr[hw * 9 + t];
@@ -218,54 +227,76 @@ __global__ __launch_bounds__(256) void conv_bwd_w_kernel(
             for (int ci = 0; ci < CI16; ++ci) xs[tid * XS + ci] = 0;
             for (int co = 0; co < COUT; ++co) ds[tid * DS + co] = 0;
         }
-    }
-    __syncthreads();
-    constexpr int MB = COUT / 16, NBc = CI16 / 16;
-    const int wv = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
-    for (int pair = wv; pair < MB * NBc; pair += WAVES) {
-        const int mb = pair / NBc, nb = pair % NBc;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int kb = 0; kb < WCHUNK; kb += 32) {
-            u16x8 av, bv;
+        __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int px = kb + 8 * g + j;
-                av[j] = ds[px * DS + mb * 16 + m];
-                bv[j] = xs[px * XS + nb * 16 + m];
-            }
-            acc = mfma(av, bv, acc);
-        }
-        const int ci = nb * 16 + m;
-        if (ci < CIN) {
+        for (int j = 0; j < NPAIR; ++j) {
+            const int pair = wv + WAVES * j;
+            if (pair < MB * NBc) {
+                const int mb = pair / NBc, nb = pair % NBc;
+                for (int kb = 0; kb < WCHUNK; kb += 32) {
+                    u16x8 av, bv;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int co = mb * 16 + 4 * g + i;
-                part[(((size_t)chunk * 9 + t) * COUT + co) * CIN + ci] = acc[i];
+                    for (int i = 0; i < 8; ++i) {
+                        const int px = kb + 8 * g + i;
+                        av[i] = ds[px * DS + mb * 16 + m];
+                        bv[i] = xs[px * XS + nb * 16 + m];
+                    }
+                    acc[j] = mfma(av, bv, acc[j]);
+                }
             }
         }
+        if (t == 4 && tid < COUT)
+            for (int i = 0; i < WCHUNK; ++i) sb += from_bf16(ds[i * DS + tid]);
+        __syncthreads();                       // the slices are overwritten next
     }
-    if (t == 4 && tid < COUT) {
-        float sb = 0.f;
-        for (int i = 0; i < WCHUNK; ++i) sb += from_bf16(ds[i * DS + tid]);
-        partb[(size_t)chunk * COUT + tid] = sb;
+#pragma unroll
+    for (int j = 0; j < NPAIR; ++j) {
+        const int pair = wv + WAVES * j;
+        if (pair < MB * NBc) {
+            const int mb = pair / NBc, nb = pair % NBc;
+            const int ci = nb * 16 + m;
+            if (ci < CIN) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int co = mb * 16 + 4 * g + i;
+                    part[(((size_t)chunk * 9 + t) * COUT + co) * CIN + ci] = acc[j][i];
+                }
+            }
+        }
     }
+    if (t == 4 && tid < COUT) partb[(size_t)chunk * COUT + tid] = sb;
 }
 
-__global__ void reduce_w_kernel(const float* __restrict__ part, const float* __restrict__ partb,
-                                int nchunk, int cin, int cout, float* __restrict__ dw,
-                                float* __restrict__ db) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the chunks' partials, in a fixed order: block b takes 64 consecutive
+// partial entries (weights in the partials' order, then the biases); wave w
+// adds chunks w, w + 16, w + 32, ... in turn, and the 16 wave sums are added in
+// wave order.
+constexpr int RW_WAVES = 16;
+__global__ __launch_bounds__(64 * RW_WAVES) void reduce_w_kernel(
+    const float* __restrict__ part, const float* __restrict__ partb, int nchunk, int cin, int cout,
+    float* __restrict__ dw, float* __restrict__ db) {
+    __shared__ float sh[RW_WAVES][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nw = cout * 9 * cin;
-    if (i < nw) {
-        const int co = i / (9 * cin), r = i - co * 9 * cin, t = r / cin, ci = r - t * cin;
-        float s = 0.f;
-        for (int c = 0; c < nchunk; ++c) s += part[(((size_t)c * 9 + t) * cout + co) * cin + ci];
-        dw[i] = s;
-    } else if (i < nw + cout) {
-        const int co = i - nw;
-        float s = 0.f;
-        for (int c = 0; c < nchunk; ++c) s += partb[(size_t)c * cout + co];
-        db[co] = s;
+    const int e = blockIdx.x * 64 + lane;       // entry: weight (partials' order) or bias
+    float s = 0.f;
+    if (e < nw) {
+        for (int c = wv; c < nchunk; c += RW_WAVES) s += part[(size_t)c * nw + e];
+    } else if (e < nw + cout) {
+        for (int c = wv; c < nchunk; c += RW_WAVES) s += partb[(size_t)c * cout + (e - nw)];
+    }
+    sh[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0) {
+        float tot = sh[0][lane];
+        for (int w = 1; w < RW_WAVES; ++w) tot += sh[w][lane];
+        if (e < nw) {
+            // partial order (t, co, ci) -> weight order (co, t, ci)
+            const int t = e / (cout * cin), r = e - t * cout * cin, co = r / cin, ci = r - co * cin;
+            dw[(size_t)co * 9 * cin + t * cin + ci] = tot;
+        } else if (e < nw + cout) {
+            db[e - nw] = tot;
+        }
     }
 }
 
@@ -566,7 +597,7 @@ vlbm_status vlbm_clo_conv_backward_weight(vlbm_clo* c, int cin, int cout, int ba
     if (!x || !dz || !dw || !db) return err(VLBM_ERR_ARG, "NULL tensor");
     if (!shape_ok(cin, cout)) return err(VLBM_ERR_ARG, "layer shape %d -> %d", cin, cout);
     const int HW = c->H * c->W, P = HW * batch;
-    const int nchunk = (P + WCHUNK - 1) / WCHUNK;
+    const int nchunk = (P + WSUB * WCHUNK - 1) / (WSUB * WCHUNK);
     float* part = reinterpret_cast<float*>(c->ws + c->L.part);
     float* partb = reinterpret_cast<float*>(c->ws + c->L.partb);
     vlbm_status st = by_shape(cin, cout, [&](auto ci, auto co) {
@@ -580,8 +611,8 @@ vlbm_status vlbm_clo_conv_backward_weight(vlbm_clo* c, int cin, int cout, int ba
     });
     if (st) return st;
     const int n = cout * 9 * cin + cout;
-    hipLaunchKernelGGL(reduce_w_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, part, partb,
-                       nchunk, cin, cout, dw, db);
+    hipLaunchKernelGGL(reduce_w_kernel, dim3((n + 63) / 64), dim3(64 * RW_WAVES), 0, c->stream, part,
+                       partb, nchunk, cin, cout, dw, db);
     return launched();
 }
 
