@@ -346,7 +346,8 @@ def run_closure():
         last = lambda name, key: round(r[name]["errors"][key][-1][1], 5)
         out = {"workload": "decaying turbulence, coarse 32x64 FP32 (+closure) vs fine 256x512 FP32 "
                            f"filtered 8x; 32 training / 8 held-out seeds, t = 0.2; inputs rho, u, T; "
-                           f"correction every {k} coarse step{'s' if k > 1 else ''}",
+                           f"correction every {k} coarse step{'s' if k > 1 else ''}; trained on "
+                           f"restart pairs + {cfg.rollout_rounds} round of rollout pairs",
                "correction_interval_steps": k,
                "train_loss_first_last": [round(x, 4) for x in r["loss_first_last"]]}
         for name in ("coarse", "closure"):

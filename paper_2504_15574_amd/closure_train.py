@@ -13,9 +13,21 @@ Setting (all runs on one device, every step of every run in the library):
 The closure acts once per interval of k coarse steps (k = 1: every step): the
 coarse run advances k steps, the network maps its moments (rho - 1, u, T - 1)
 to a correction (d_rho, d_u), and the correction enters the populations
-through the equilibrium (vlbm_correct_moments).  Training pairs come from the fine runs: the input is
-the coarse run's state one interval after it started from the filtered fine
-state X_n, the target the filtered fine state X_{n+1} minus that prediction.
+through the equilibrium (vlbm_correct_moments).  Training pairs come from the
+fine runs: the input is the coarse run's state one interval after it started
+from the filtered fine state X_n (rho, u and the mass-weighted temperature),
+the target the filtered fine state X_{n+1} minus that prediction.  A network
+trained on such pairs alone only ever sees states one interval away from a
+filtered fine state; in a rollout its own corrections move the state away from
+that set, and with a correction every step the errors compound until the run
+blows up.  So after the first fit the closure is rolled out on the training
+seeds (rollout_rounds times), restarted from the filtered fine state every
+rollout_steps coarse steps: the states it reaches, one interval after each
+correction, become further inputs, with the filtered fine state at the same
+time as target, and the network is trained on all pairs again.  A rollout
+stops collecting once its targets leave the range the first fit was scaled
+for (rms above rollout_cap output units), so a run that drifts far does not
+swamp the loss.
 
 Evaluation compares, on held-out seeds, the plain coarse run and the coarse run
 with the closure against the filtered fine run: relative L2 of vorticity and of
@@ -49,6 +61,9 @@ class Config:
     train_seeds: list = field(default_factory=lambda: list(range(1000, 1032)))
     eval_seeds: list = field(default_factory=lambda: list(range(2000, 2008)))
     iters: int = 1500
+    rollout_rounds: int = 1      # refits on pairs collected from closure rollouts
+    rollout_steps: int = 50      # coarse steps between restarts of those rollouts
+    rollout_cap: float = 4.0     # largest rms target (output units) collected
     minibatch: int = 32
     lr: float = 2e-3
     seed: int = 0
@@ -72,9 +87,9 @@ def fine_substeps(cfg):
     return max(1, math.ceil(cfg.dt_c / dmax * (1 + 1e-12)))
 
 
-def _fields(n, H, W):
+def _fields(n, H, W, c=3):
     import torch
-    return [torch.zeros((n, H, W), dtype=torch.float64, device="cuda") for _ in range(3)]
+    return [torch.zeros((n, H, W), dtype=torch.float64, device="cuda") for _ in range(c)]
 
 
 class _Events:
@@ -96,8 +111,9 @@ class _Events:
 
 
 def fine_filtered(cfg, seeds, storage="f32"):
-    """Filtered fine states X[n] (n = 0..intervals) for the seeds: three FP64
-    device tensors per interval, [len(seeds)][n_theta_c][n_phi_c] each.  Also
+    """Filtered fine states X[n] (n = 0..intervals) for the seeds: four FP64
+    device tensors per interval (rho, u_theta, u_phi, T), each
+    [len(seeds)][n_theta_c][n_phi_c]; T is the mass-weighted box average.  Also
     returns the fine cost in ms of device time per run per unit simulated time."""
     import workloads as W
     from .closure import vlbm_box_filter
@@ -106,7 +122,7 @@ def fine_filtered(cfg, seeds, storage="f32"):
     dt_f = cfg.dt_c / sub
     Hf, Wf, Hc, Wc = cfg.n_theta_f, cfg.n_phi_f, cfg.n_theta_c, cfg.n_phi_c
     N = len(seeds)
-    X = [_fields(N, Hc, Wc) for _ in range(cfg.intervals + 1)]
+    X = [_fields(N, Hc, Wc, 4) for _ in range(cfg.intervals + 1)]
     clock = _Events()
     for i0 in range(0, N, cfg.batch):
         chunk = seeds[i0:i0 + cfg.batch]
@@ -115,11 +131,16 @@ def fine_filtered(cfg, seeds, storage="f32"):
         for s, sd in zip(sols, chunk):
             s.init_fields(*W.turbulence_state(Hf, Wf, seed=sd, lmax=cfg.lmax, urms=cfg.urms)[:3])
         ens = Ensemble(sols)
-        mom = _fields(B, Hf, Wf)
+        mom = _fields(B, Hf, Wf, 4)
+        spare = _fields(B, Hc, Wc, 1)[0]
         for n in range(cfg.intervals + 1):
             for b, s in enumerate(sols):
-                s.moments_device(mom[0][b], mom[1][b], mom[2][b])
-            vlbm_box_filter(Hf, Wf, cfg.factor, B, *mom, *[x[i0:i0 + B] for x in X[n]])
+                s.moments_device(mom[0][b], mom[1][b], mom[2][b], mom[3][b])
+            Xn = [x[i0:i0 + B] for x in X[n]]
+            vlbm_box_filter(Hf, Wf, cfg.factor, B, *mom[:3], *Xn[:3])
+            # (rho, T, T) through the same filter: the momentum-weighted channel
+            # of T is its mass-weighted average
+            vlbm_box_filter(Hf, Wf, cfg.factor, B, mom[0], mom[3], mom[3], spare, Xn[3], spare)
             if n < cfg.intervals:
                 with clock:
                     ens.step(cfg.k * sub)
@@ -138,13 +159,13 @@ class CoarsePool:
         self.sols = [Solver(cfg.n_theta_c, cfg.n_phi_c, cfg.tau, cfg.dt_c, storage="f32")
                      for _ in range(B)]
         self.ens = Ensemble(self.sols)
-        self.mom = _fields(B, cfg.n_theta_c, cfg.n_phi_c) + _fields(B, cfg.n_theta_c, cfg.n_phi_c)[:1]
+        self.mom = _fields(B, cfg.n_theta_c, cfg.n_phi_c, 4)
         self.corr = _fields(B, cfg.n_theta_c, cfg.n_phi_c)
 
     def load(self, X, idx=None):
         for b, s in enumerate(self.sols):
             j = b if idx is None else int(idx[b])
-            s.init_fields_device(X[0][j], X[1][j], X[2][j])
+            s.init_fields_device(X[0][j], X[1][j], X[2][j], X[3][j])
 
     def moments(self, out=None):
         """rho, u_theta, u_phi and T of every run."""
@@ -157,49 +178,79 @@ class CoarsePool:
         """k coarse steps, then the closure correction (if a network is given)."""
         self.ens.step(self.cfg.k)
         if net is not None:
-            m = self.moments()
-            net.pack_input(self.B, *m[:3], stats["s_rho"], stats["s_u"], T=m[3], s_T=stats["s_T"])
-            net.forward(self.B)
-            net.unpack_output(self.B, stats["o_rho"], stats["o_u"], *self.corr)
-            for b, s in enumerate(self.sols):
-                s.correct_moments_device(self.corr[0][b], self.corr[1][b], self.corr[2][b])
+            self.correct(net, stats, self.moments())
+
+    def correct(self, net, stats, m):
+        """Apply the network's correction for the moments m of every run."""
+        net.pack_input(self.B, *m[:3], stats["s_rho"], stats["s_u"], T=m[3], s_T=stats["s_T"])
+        net.forward(self.B)
+        net.unpack_output(self.B, stats["o_rho"], stats["o_u"], *self.corr)
+        for b, s in enumerate(self.sols):
+            s.correct_moments_device(self.corr[0][b], self.corr[1][b], self.corr[2][b])
 
     def close(self):
         for s in self.sols:
             s.close()
 
 
-def build_dataset(cfg, X):
-    """Inputs Y_n (coarse state one interval after X_n) and targets X_{n+1}."""
+def build_dataset(cfg, X, net=None, stats=None):
+    """Inputs Y_n and targets X_{n+1}.  Without a network Y_n is the coarse
+    state one interval after a restart from X_n.  With one, the runs restart
+    from X_n every rollout_steps coarse steps and Y_n is the state one interval
+    after the previous correction of the closure rollout; a rollout stops
+    collecting (until its next restart) at the first interval whose rms target
+    exceeds rollout_cap in output units."""
     import torch
     N = X[0][0].shape[0]
     pool = CoarsePool(cfg, N)
     Y, T = [], []
+    every = 1 if net is None else max(1, cfg.rollout_steps // cfg.k)
+    live = True
     for n in range(cfg.intervals):
-        pool.load(X[n])
-        pool.interval()
-        Y.append([t.clone() for t in pool.moments()])
-        T.append(X[n + 1])
+        if n % every == 0:
+            pool.load(X[n])
+            live = True
+        if not live:
+            continue
+        pool.ens.step(cfg.k)
+        m = pool.moments()
+        if net is not None:
+            d = [(X[n + 1][c] - m[c]) / (stats["o_rho"] if c == 0 else stats["o_u"]) for c in range(3)]
+            rms = math.sqrt(sum(float((x * x).mean()) for x in d) / 3)
+            if not rms <= cfg.rollout_cap:       # also false for a run that blew up
+                live = False
+                continue
+        Y.append([t.clone() for t in m])
+        T.append(X[n + 1][:3])
+        if net is not None:
+            pool.correct(net, stats, m)
     pool.close()
     cat = lambda L, c: torch.cat([x[c] for x in L], 0).contiguous()
     return [cat(Y, c) for c in range(4)], [cat(T, c) for c in range(3)]
 
 
-def fit(cfg, Y, T, log=None):
-    """Train the network on (Y, T); returns (net, stats, loss history)."""
+def fit(cfg, Y, T, log=None, net=None, stats=None):
+    """Train the network on (Y, T); returns (net, stats, loss history).  A
+    network and its input/output scales passed in are trained further."""
     import torch
     from .closure import ClosureNet
     M = Y[0].shape[0]
-    d = [T[c] - Y[c] for c in range(3)]
-    sT = float((Y[3] - 1.0).std())
-    stats = {"s_rho": 1.0 / float((Y[0] - 1.0).std()), "s_u": 1.0 / float(torch.cat([Y[1], Y[2]]).std()),
-             "s_T": 1.0 / sT if sT > 0 else 0.0,
-             "o_rho": float(d[0].std()), "o_u": float(torch.cat([d[1], d[2]]).std())}
+    if stats is None:
+        d = [T[c] - Y[c] for c in range(3)]
+        sT = float((Y[3] - 1.0).std())
+        stats = {"s_rho": 1.0 / float((Y[0] - 1.0).std()),
+                 "s_u": 1.0 / float(torch.cat([Y[1], Y[2]]).std()),
+                 "s_T": 1.0 / sT if sT > 0 else 0.0,
+                 "o_rho": float(d[0].std()), "o_u": float(torch.cat([d[1], d[2]]).std())}
+        del d
     mb = min(cfg.minibatch, M)
-    net = ClosureNet(cfg.n_theta_c, cfg.n_phi_c, mb, seed=cfg.seed)
+    if net is None:
+        # capacity for a minibatch and for the rollouts of all training or held-out runs
+        cap = max(mb, len(cfg.train_seeds), len(cfg.eval_seeds))
+        net = ClosureNet(cfg.n_theta_c, cfg.n_phi_c, cap, seed=cfg.seed)
     target = torch.zeros(mb * cfg.n_theta_c * cfg.n_phi_c * 3, dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(cfg.seed)
-    bufY = _fields(mb, cfg.n_theta_c, cfg.n_phi_c) + _fields(mb, cfg.n_theta_c, cfg.n_phi_c)[:1]
+    bufY = _fields(mb, cfg.n_theta_c, cfg.n_phi_c, 4)
     bufT = _fields(mb, cfg.n_theta_c, cfg.n_phi_c)
     hist = []
     for it in range(cfg.iters):
@@ -318,6 +369,7 @@ def run(cfg, log=print, ks=None):
     (default: cfg.k) over the same simulated time cfg.intervals * cfg.k coarse
     steps.  The fine runs are made once, filtered at the finest interval;
     returns {k: result} (or the result of cfg.k alone when ks is None)."""
+    import torch
     single = ks is None
     ks = [cfg.k] if single else list(ks)
     steps = cfg.intervals * cfg.k
@@ -343,6 +395,13 @@ def run(cfg, log=print, ks=None):
         Xtr, Xev = Xtr_all[::sub], Xev_all[::sub]
         Y, T = build_dataset(ck, Xtr)
         net, stats, hist = fit(ck, Y, T, log)
+        for _ in range(cfg.rollout_rounds):
+            Yr, Tr = build_dataset(ck, Xtr, net, stats)
+            Y = [torch.cat([a, b], 0) for a, b in zip(Y, Yr)]
+            T = [torch.cat([a, b], 0) for a, b in zip(T, Tr)]
+            del Yr, Tr
+            net, stats, h2 = fit(ck, Y, T, log, net, stats)
+            hist += h2
         del Y, T
         log(f"k = {k}: trained in {time.time() - t1:.1f} s")
         res = evaluate(ck, net, stats, Xev, fine_ms_ev)

@@ -308,9 +308,10 @@ class Solver:
         self.t += n * self.dt
 
     # fields already in device memory: contiguous FP64 torch tensors [n_theta, n_phi]
-    def init_fields_device(self, rho, ut, up):
+    def init_fields_device(self, rho, ut, up, T=None):
         n = self.n_theta * self.n_phi
-        vlbm_init_fields(self.ctx, _dptr(rho, n), _dptr(ut, n), _dptr(up, n), None, 1)
+        vlbm_init_fields(self.ctx, _dptr(rho, n), _dptr(ut, n), _dptr(up, n),
+                         _dptr(T, n) if T is not None else None, 1)
         self.t = 0.0
 
     def moments_device(self, rho, ut, up, T=None):
