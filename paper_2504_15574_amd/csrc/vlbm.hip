@@ -407,11 +407,13 @@ constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
 // three waves without) and ran 25 % (8 %) slower than stage_tile at five.
 template <class T, class Tl, int VAR, int NQ>
 constexpr bool uses_rounds() { return sizeof(T) != 8 && Tl::TS == 15 && VAR == VAR_WENO && NQ == 4; }
-// minimum waves per SIMD of a stage launch (the rounds kernel: six, at most
-// 80 VGPRs; seven would spill)
-template <class T, class Tl, int VAR, int NQ>
+// minimum waves per SIMD of a stage launch (the rounds kernel: seven for
+// FP32, whose direct-to-LDS loads hold nothing in registers, at most 72 VGPRs
+// and 23 KB of LDS per workgroup; six for FP16, at most 80 VGPRs: seven would
+// spill)
+template <class St, class Tl, int VAR, int NQ>
 constexpr int launch_min_waves() {
-    return uses_rounds<T, Tl, VAR, NQ>() ? 6 : stage_min_waves<T, VAR>();
+    return uses_rounds<typename St::T, Tl, VAR, NQ>() ? (St::B == 4 ? 7 : 6) : stage_min_waves<typename St::T, VAR>();
 }
 // The end of a stage for one cell: BGK's equilibrium part from the cell's
 // moments, the SSP-RK3 combination and the store in the storage format.  acc
@@ -876,17 +878,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
 //
 // The populations are taken four at a time in the rounds of ROUND_ORDER, whose
 // members share the signs of both speed components, so every flux of a round
-// is upwinded the same way.  A round's four cross-shaped tiles sit in LDS
-// together.  Wave w computes the theta fluxes of interface rows 4w .. 4w+3 of
+// is upwinded the same way.  A round's four tiles sit in LDS together.  Wave
+// w computes the theta fluxes of interface rows 4w .. 4w+3 of
 // all four populations (lane = population x column), walking down its column:
 // the eight stencil rows are read once for four interfaces, sin(theta) of a row
 // is the same for the whole wave, and the differences the interfaces share are
 // formed once.  The phi fluxes go the same way along the rows (lane =
 // population x row; interfaces 4w .. 4w+3, wave 3 also the tile's right edge).
 // Then the 240 cell threads read the four faces of each of the round's
-// populations and accumulate as in stage_tile.  The next round's loads are in
-// flight meanwhile and are written to LDS once the fluxes have been read: two
-// barriers per round, eight per stage.
+// populations and accumulate as in stage_tile.  The loads of later rounds are
+// in flight meanwhile (FP32: straight into a second tile set; FP16: in
+// registers, written to LDS once the fluxes have been read): two barriers per
+// round, eight per stage.
 template <class T>
 __device__ __forceinline__ T scalar_load(const T* p, int i) {
     // the row tables are written before any launch and only read by kernels:
@@ -902,19 +905,34 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, NLOAD = Tl::NLOAD;
     using T = typename St::T;
     constexpr int B = St::B;
-    // LDS tile of one population: LR rows of pitch 23 (odd, so that the 16 rows
-    // of a phi read fall on distinct banks), the unused last column of row 0
-    // takes the writes of unused load slots
-    constexpr int PITCH = 23, PSZ = LR * PITCH, DUMMY = PITCH - 1;
+    // FP32 (a stored value is the arithmetic value) fills its tiles with
+    // direct-to-LDS loads, so no registers hold the coming rounds in flight:
+    // the tile is the full LR x LC rectangle, row-major with pitch LC = 22,
+    // taken dword by dword (lane i of a wave writes dword i past the wave's
+    // base), each dword at its own folded address, so pole rows and the phi
+    // wrap need no special case.  Two tile sets alternate between rounds, so
+    // the loads of round r + 2 are issued while round r + 1 is computed.  The
+    // 16 rows of a phi read (22 dwords apart) fall on distinct banks; the
+    // populations' tiles are 464 dwords apart (16 modulo 64 banks), so the
+    // four 16-lane groups of a theta read take disjoint banks.  FP16
+    // (converted and scaled on the way in) keeps one cross-shaped tile set of
+    // pitch 23 filled through registers; the unused last column of row 0
+    // takes the writes of unused load slots.
+    constexpr bool DMA = B == (int)sizeof(T) && sizeof(T) == 4;
+    constexpr int LC = TQ + 2 * NGH;
+    constexpr int PITCH = DMA ? LC : 23, PSZ = DMA ? 464 : LR * PITCH, DUMMY = PITCH - 1;
+    constexpr int NDW = LR * LC, NSL = (NDW + NTHR - 1) / NTHR;   // dwords of a DMA tile, per thread
+    static_assert(!DMA || (LR * LC <= PSZ && NSL == 2), "direct-to-LDS tile");
     constexpr int FTP = (TS + 1) * TQ;          // theta faces of a population
     constexpr int FPR = TQ + 1, FPP = TS * FPR;  // phi faces per row, per population
-    __shared__ T tile[4 * PSZ];
+    constexpr int NBUF = DMA ? 2 : 1;            // FP32: rounds alternate between two tile sets
+    __shared__ T tile[NBUF * 4 * PSZ];
     __shared__ T fth[4 * FTP];
     __shared__ T fph[4 * FPP];
 
     const ConstsT<T>& C = consts_of<T>(A);
     const int tid = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave of the workgroup
     const int lp = (tid & 63) >> 4, l16 = tid & 15;
     const int nt = D.nt, np = D.np;
     const int tq = (np + TQ - 1) / TQ;
@@ -923,18 +941,22 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     const int half = np > 1 ? np / 2 : 0;
     const rsrc_t rin = make_rsrc(D.gin, NK * planeB);
 
-    // ---- load descriptors (as stage_tile): two cross-shaped positions per
-    // thread; population k at byte offset (k planeB ^ m) + a
+    // ---- load descriptors (as stage_tile): two positions per thread (FP32:
+    // dwords tid and tid + 256 of the rectangle, FP16: cross-shaped
+    // positions); population k at byte offset (k planeB ^ m) + a
     uint32_t la[2], lm[2];
     int ldst[2];
     const bool inner = s0 >= NGH && s0 + TS + NGH <= nt && q0 >= NGH && q0 + TQ + NGH <= np;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         int idx = tid + NTHR * j;
-        const bool used = idx < NLOAD;
+        const bool used = idx < (DMA ? NDW : NLOAD);
         if (!used) idx = 0;
         int r, c;
-        if (idx < LR * TQ) {
+        if constexpr (DMA) {
+            r = idx / LC;
+            c = idx % LC;
+        } else if (idx < LR * TQ) {
             r = idx / TQ;
             c = idx % TQ + NGH;
         } else {
@@ -1008,24 +1030,52 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     auto wrk = [&](int kt, int kp) { return FOLD ? Cwr[fold(kt) * NH + fold(kp)] : Cwr[kt * NQ + kp]; };
 
     // the loads of round r: population ROUND_ORDER[4 r + p] of both positions
+    // (FP32: straight into LDS, at dwords j 256 + 64 w + lane of the tile)
     T nx[4][2];
     auto issue = [&](int r) {
+        if constexpr (DMA) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            nx[p][0] = gload(ROUND_ORDER[4 * r + p], 0);
-            nx[p][1] = gload(ROUND_ORDER[4 * r + p], 1);
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t kb = (uint32_t)ROUND_ORDER[4 * r + p] * planeB;
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    if (NTHR * j + tid < NDW)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            rin,
+                            (__attribute__((address_space(3))) void*)(tile + ((r & 1) * 4 + p) * PSZ + NTHR * j + 64 * w),
+                            4, (kb ^ lm[j]) + la[j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                nx[p][0] = gload(ROUND_ORDER[4 * r + p], 0);
+                nx[p][1] = gload(ROUND_ORDER[4 * r + p], 1);
+            }
         }
     };
     auto put = [&]() {
+        if constexpr (!DMA) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            tile[p * PSZ + ldst[0]] = nx[p][0];
-            tile[p * PSZ + ldst[1]] = nx[p][1];
+            for (int p = 0; p < 4; ++p) {
+                tile[p * PSZ + ldst[0]] = nx[p][0];
+                tile[p * PSZ + ldst[1]] = nx[p][1];
+            }
+        }
+    };
+    // direct-to-LDS loads count in vmcnt, in issue order, eight per round and
+    // wave: before the barrier that makes a round's tiles visible, the wave
+    // waits until at most the eight of the round after it are outstanding
+    // (vmcnt 8 or 0; expcnt, lgkmcnt unchanged)
+    auto dma_done = [&](bool newer) {
+        if constexpr (DMA) {
+            if (newer) __builtin_amdgcn_s_waitcnt(0x0f78);
+            else __builtin_amdgcn_s_waitcnt(0x0f70);
         }
     };
     issue(0);
     put();
     issue(1);
+    dma_done(true);
     __syncthreads();
 
     const FaceRowK<T>* fkt = static_cast<const FaceRowK<T>*>(D.facek);
@@ -1043,13 +1093,18 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     for (int r = 0; r < 4; ++r) {
         const int st = r < 2 ? -1 : 1;              // sign of v_theta in this round
         const int sp = (r & 1) ? 1 : -1;            // sign of v_phi
-        const T* tl = tile + lp * PSZ;
-        // -- the cell's own values of the round's populations
+        const T* tl = tile + ((DMA ? (r & 1) * 4 : 0) + lp) * PSZ;
+        const T* rt = tile + (DMA ? (r & 1) * 4 : 0) * PSZ;         // the round's tiles
+        // -- the cell's own values of the round's populations (FP32: after the
+        // fluxes; the next round's loads overwrite the tiles after the barrier)
         T gself[4];
-        if (cell) {
+        auto read_self = [&]() {
+            if (cell) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) gself[p] = tile[p * PSZ + (cr + NGH) * PITCH + cc + NGH];
-        }
+                for (int p = 0; p < 4; ++p) gself[p] = rt[p * PSZ + (cr + NGH) * PITCH + cc + NGH];
+            }
+        };
+        if constexpr (!DMA) read_self();
         // -- theta fluxes: population lp, column l16, interface rows 4w .. 4w+3
         {
             // the rest weight of this lane's population (a select, not a
@@ -1111,9 +1166,13 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
             for (int f = 0; f < 4; ++f) face(f);
             if (w == 3) face(4);
         }
+        if constexpr (DMA) read_self();
         __syncthreads();
-        // -- the next round's tile, then its successor's loads
-        if (r < 3) {
+        // -- the next round's tile, then its successor's loads (FP32: the loads
+        // of the round after next, into the tile set this round has finished)
+        if constexpr (DMA) {
+            if (r < 2) issue(r + 2);
+        } else if (r < 3) {
             put();
             if (r < 2) issue(r + 2);
         }
@@ -1153,7 +1212,10 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
                 }
             }
         }
-        if (r < 3) __syncthreads();
+        if (r < 3) {
+            dma_done(r < 2);
+            __syncthreads();
+        }
     }
     if (!valid) return;
     stage_epilogue<St, NQ>(D, C, acc, gk, drho, jt, jp, cs, cq, ctr);
@@ -1177,7 +1239,7 @@ __device__ __forceinline__ int run_of(const StageArgs& A, int tg) {
 // its run from the kernel arguments; a batched one looks up the run of its
 // tile (uniform per workgroup).
 template <class St, bool BATCH, class Tl, int VAR, int NQ>
-__global__ __launch_bounds__(NTHR, (launch_min_waves<typename St::T, Tl, VAR, NQ>())) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(NTHR, (launch_min_waves<St, Tl, VAR, NQ>())) void stage_kernel(StageArgs A) {
     const int nall = A.tile_start[A.nruns];
     const int per = (nall + 7) / 8;
     const int tg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
