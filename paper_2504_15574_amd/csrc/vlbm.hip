@@ -407,13 +407,13 @@ constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
 // three waves without) and ran 25 % (8 %) slower than stage_tile at five.
 template <class T, class Tl, int VAR, int NQ>
 constexpr bool uses_rounds() { return sizeof(T) != 8 && Tl::TS == 15 && VAR == VAR_WENO && NQ == 4; }
-// minimum waves per SIMD of a stage launch (the rounds kernel: seven for
-// FP32, whose direct-to-LDS loads hold nothing in registers, at most 72 VGPRs
-// and 23 KB of LDS per workgroup; six for FP16, at most 80 VGPRs: seven would
-// spill)
-template <class St, class Tl, int VAR, int NQ>
+// minimum waves per SIMD of a stage launch (the rounds kernel: seven with
+// direct-to-LDS loads, which hold nothing in registers, at most 72 VGPRs and
+// 23 KB of LDS per workgroup; six, at most 80 VGPRs, when loading through
+// registers: seven would spill)
+template <class St, class Tl, int VAR, int NQ, bool LDSDMA>
 constexpr int launch_min_waves() {
-    return uses_rounds<typename St::T, Tl, VAR, NQ>() ? (St::B == 4 ? 7 : 6) : stage_min_waves<typename St::T, VAR>();
+    return uses_rounds<typename St::T, Tl, VAR, NQ>() ? (LDSDMA ? 7 : 6) : stage_min_waves<typename St::T, VAR>();
 }
 // The end of a stage for one cell: BGK's equilibrium part from the cell's
 // moments, the SSP-RK3 combination and the store in the storage format.  acc
@@ -898,15 +898,16 @@ __device__ __forceinline__ T scalar_load(const T* p, int i) {
     return ((const __attribute__((address_space(4))) T*)p)[i];
 }
 
-template <class St>
+template <class St, bool LDSDMA>
 __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunDesc& D, int t, uint32_t ctr) {
     using Tl = Tile15x16;
     constexpr int NQ = 4, NK = 16;
     constexpr int TS = Tl::TS, TQ = Tl::TQ, LR = Tl::LR, NLOAD = Tl::NLOAD;
     using T = typename St::T;
     constexpr int B = St::B;
-    // FP32 (a stored value is the arithmetic value) fills its tiles with
-    // direct-to-LDS loads, so no registers hold the coming rounds in flight:
+    // FP32 on one large run (a stored value is the arithmetic value) fills
+    // its tiles with direct-to-LDS loads, so no registers hold the coming
+    // rounds in flight:
     // the tile is the full LR x LC rectangle, row-major with pitch LC = 22,
     // taken dword by dword (lane i of a wave writes dword i past the wave's
     // base), each dword at its own folded address, so pole rows and the phi
@@ -915,10 +916,11 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     // 16 rows of a phi read (22 dwords apart) fall on distinct banks; the
     // populations' tiles are 464 dwords apart (16 modulo 64 banks), so the
     // four 16-lane groups of a theta read take disjoint banks.  FP16
-    // (converted and scaled on the way in) keeps one cross-shaped tile set of
-    // pitch 23 filled through registers; the unused last column of row 0
-    // takes the writes of unused load slots.
-    constexpr bool DMA = B == (int)sizeof(T) && sizeof(T) == 4;
+    // (converted and scaled on the way in), batches of runs and small runs
+    // keep one cross-shaped tile set of pitch 23 filled through registers;
+    // the unused last column of row 0 takes the writes of unused load slots.
+    constexpr bool DMA = LDSDMA;
+    static_assert(!DMA || (B == (int)sizeof(T) && sizeof(T) == 4), "direct-to-LDS loads copy FP32 values");
     constexpr int LC = TQ + 2 * NGH;
     constexpr int PITCH = DMA ? LC : 23, PSZ = DMA ? 464 : LR * PITCH, DUMMY = PITCH - 1;
     constexpr int NDW = LR * LC, NSL = (NDW + NTHR - 1) / NTHR;   // dwords of a DMA tile, per thread
@@ -1237,9 +1239,10 @@ __device__ __forceinline__ int run_of(const StageArgs& A, int tg) {
 // over the 8 XCDs) take a contiguous range of tiles, keeping halo rows and the
 // 64-byte halves of shared cache lines inside one L2.  A single-run launch reads
 // its run from the kernel arguments; a batched one looks up the run of its
-// tile (uniform per workgroup).
-template <class St, bool BATCH, class Tl, int VAR, int NQ>
-__global__ __launch_bounds__(NTHR, (launch_min_waves<St, Tl, VAR, NQ>())) void stage_kernel(StageArgs A) {
+// tile (uniform per workgroup).  LDSDMA: the rounds kernel's direct-to-LDS
+// form (FP32).
+template <class St, bool BATCH, class Tl, int VAR, int NQ, bool LDSDMA = false>
+__global__ __launch_bounds__(NTHR, (launch_min_waves<St, Tl, VAR, NQ, LDSDMA>())) void stage_kernel(StageArgs A) {
     const int nall = A.tile_start[A.nruns];
     const int per = (nall + 7) / 8;
     const int tg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -1248,7 +1251,7 @@ __global__ __launch_bounds__(NTHR, (launch_min_waves<St, Tl, VAR, NQ>())) void s
     const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
     const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr;
     if constexpr (uses_rounds<typename St::T, Tl, VAR, NQ>())
-        stage_tile_rounds<St>(A, D, tg - A.tile_start[run], ctr);
+        stage_tile_rounds<St, LDSDMA>(A, D, tg - A.tile_start[run], ctr);
     else
         stage_tile<St, Tl, VAR, NQ>(A, D, tg - A.tile_start[run], ctr);
 }
@@ -2111,6 +2114,17 @@ vlbm_status launch_group(vlbm_ctx* const* xs, int m, int stage, hipStream_t stre
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
+    // a single FP32 run of at least 2048 15 x 16 tiles takes the rounds
+    // kernel's direct-to-LDS form, which pays off on large grids only
+    // (single-run MLUPS against the register form: 256 x 512 -3.6 %,
+    // 512 x 1024 and 1024 x 2048 equal, 1536 x 3072 +1.1 %, 2048 x 4096 +0.5 %)
+    constexpr int DMA_MIN_TILES = 2048;
+    if constexpr (std::is_same<St, StF32>::value && VAR == VAR_WENO) {
+        if (m == 1 && !wide && nb >= DMA_MIN_TILES) {
+            hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR_WENO, 4, true>), grid, dim3(NTHR), 0, stream, A);
+            return launch_check();
+        }
+    }
     if (m == 1) { if (wide) go(F_{}, Tile7x32{}); else go(F_{}, Tile15x16{}); }
     else { if (wide) go(T_{}, Tile7x32{}); else go(T_{}, Tile15x16{}); }
     return launch_check();
