@@ -56,6 +56,24 @@ def test_batched_equals_one_by_one_bitwise(storage):
         s.close()
 
 
+@pytest.mark.parametrize("shape", [(511, 1000), (512, 1024)])
+def test_direct_to_lds_form_gives_the_register_form_bits(shape):
+    # A single FP32 run of at least 2048 15 x 16 tiles takes the rounds
+    # kernel's direct-to-LDS form; inside a batch the same run takes the
+    # register form.  Ragged edges (511 x 1000: 35 x 63 tiles), pole rows and
+    # the phi wrap all go through the direct loads' folded addresses.
+    from paper_2504_15574_amd import Ensemble
+    nt, nph = shape
+    a = _runs("f32", [shape, (16, 32)], seed=5)
+    b = _runs("f32", [shape], seed=5)
+    assert ((nt + 14) // 15) * ((nph + 15) // 16) >= 2048
+    Ensemble(a).step(6)
+    b[0].step(6)
+    assert np.array_equal(a[0].populations(), b[0].populations())
+    for s in a + b:
+        s.close()
+
+
 def test_more_than_64_runs_split_into_launches():
     from paper_2504_15574_amd import Ensemble
     specs = [(8, 16)] * 40 + [(12, 32)] * 30
