@@ -396,11 +396,12 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
 enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
 // Minimum waves per SIMD the register allocation must allow: 7 for the float
 // kernels (at most 72 VGPRs; the general WENO-5 variant keeps two values in
-// scratch across the population loop and still gains 3.7 % over 6 waves), 5 for
-// FP64 (at most 96 VGPRs, which needs its row factors in LDS; its LDS use,
-// 32 KB per workgroup, also allows no more).
+// scratch across the population loop and still gains 3.7 % over 6 waves), 6
+// for FP64 (at most 80 VGPRs: its row factors in LDS, its populations loaded
+// straight into LDS with nothing in flight in registers; 24 KB of LDS per
+// workgroup, six per CU).
 template <class T, int VAR>
-constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
+constexpr int stage_min_waves() { return sizeof(T) == 8 ? 6 : 7; }
 // The float formats of D2Q16 with the WENO-5 standard form on 15 x 16 tiles
 // run stage_tile_rounds (same bits as stage_tile).  FP64 stays on stage_tile:
 // the rounds kernel needs 128 VGPRs there (four waves per SIMD, with spills;
@@ -556,11 +557,31 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     using T = typename St::T;
     constexpr int B = St::B;
     using SL = SlotLayout<Tl, (int)sizeof(T)>;
-    // the three ring slots are interleaved element by element (element i of
-    // slot b at 3 i + b): a thread's stencil reads in any slot then sit at small
-    // constant offsets from one base address, so no per-slot address arithmetic
-    __shared__ T tile[3 * SL::SIZE];           // g of one population, cross-shaped halo
-    __shared__ T tileh[3 * SL::SIZE];          // sin(theta_j) g_j: theta flux function without its speed
+    // FP64 fills its ring with direct-to-LDS loads (no registers hold the
+    // populations in flight, no LDS writes place them): each slot is the full
+    // LR x LC rectangle, row-major (SlotLayout's 8-byte form), at slot b *
+    // LR LC; an interior tile takes it as chunks of two neighbouring values,
+    // one 16-byte load per thread landing at byte 16 tid of the slot, a tile
+    // with pole rows or a phi wrap in its halo (where neighbouring halo values
+    // need not be neighbours in memory) dword by dword, with addresses formed
+    // at issue.  The theta flux function sin(theta) g is formed at the read
+    // from a table of the tile's rows.  The float formats interleave the
+    // three ring slots element by element (element i of slot b at 3 i + b): a
+    // thread's stencil reads in any slot then sit at small constant offsets
+    // from one base address, so no per-slot address arithmetic; they keep
+    // sin(theta) g in a second ring.
+    constexpr bool DMA = sizeof(T) == 8;
+    constexpr int LC = Tl::LC, LT = Tl::LT, NCH = LT / 2;
+    static_assert(!DMA || (LC % 2 == 0 && NCH <= NTHR && (LT * sizeof(T)) % 16 == 0), "FP64 ring slots");
+    __shared__ T tile[DMA ? 3 * LT : 3 * SL::SIZE];      // g of one population, cross-shaped halo
+    __shared__ T tileh[DMA ? 1 : 3 * SL::SIZE];          // sin(theta_j) g_j: theta flux function without its speed
+    __shared__ T ssin[DMA ? LR : 1];                     // sin(theta) of the tile's rows (FP64)
+    // FP64 on a tile with pole rows or a phi wrap: the byte offset of each
+    // dword of a slot (population 0, or NK - 1 on a pole row, whose offset is
+    // the only odd one: +1 marks the mirror), written and read by the thread
+    // that loads that dword
+    __shared__ uint32_t dtab[DMA ? 2 * LT : 1];
+    auto slot = [&](int b, int a) -> const T& { return DMA ? tile[b * LT + a] : tile[3 * a + b]; };
     __shared__ T fth[2][NFT];
     __shared__ T fph[2][NFP + 1];              // faces with phi index < TQ row-major, then the TS right faces
 
@@ -574,29 +595,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     const int half = np > 1 ? np / 2 : 0;
     const rsrc_t rin = make_rsrc(D.gin, NK * planeB);
 
-    // ---- load descriptors: two cross-shaped tile slots per thread.  The byte
-    // offset of population k is (k*planeB ^ m) + a: m = 0 for interior rows,
-    // m = ~0 for pole ghost rows, which then read population 15 - k.
-    uint32_t la[2], lm[2];
-    int ldst[2];
-    T lsin[2];
+    // ---- load descriptors.  The byte offset of population k at tile position
+    // (r, c) is (k*planeB ^ m) + a: m = 0 for interior rows, m = ~0 for pole
+    // ghost rows, which then read population 15 - k.
     // a tile whose halo lies inside the grid (no pole rows, no phi wrap): the
     // descriptors need no folding (uniform per workgroup)
     const bool inner = s0 >= NGH && s0 + TS + NGH <= nt && q0 >= NGH && q0 + TQ + NGH <= np;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        int idx = tid + NTHR * j;
-        const bool used = idx < NLOAD;
-        if (!used) idx = 0;
-        int r, c;
-        if (idx < LR * TQ) {
-            r = idx / TQ;
-            c = idx % TQ + NGH;
-        } else {
-            const int e = idx - LR * TQ, e2 = e % (TS * NGH);
-            r = e2 / NGH + NGH;
-            c = (e < TS * NGH) ? e2 % NGH : TQ + NGH + e2 % NGH;
-        }
+    auto locate = [&](int r, int c, uint32_t& a, uint32_t& m) {
         int ss = s0 - NGH + r, qq = q0 - NGH + c;
         bool mir = false;
         if (!inner) {
@@ -613,12 +618,79 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
             }
             ss = ss < 0 ? 0 : (ss >= nt ? nt - 1 : ss);   // rows no valid cell reads
         }
-        ldst[j] = used ? SL::at(r, c) : SL::DUMMY;
-        la[j] = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
-        lm[j] = mir ? ~0u : 0u;
-        const int js = s0 + r;                        // sin table index of row s0 - 3 + r
-        lsin[j] = T(D.rows.sinv[js < nt + 2 * NGH ? js : nt + 2 * NGH - 1]);
+        a = (uint32_t)(ss * np + qq) * B + (mir ? (uint32_t)(NK - 1) * planeB + 1u : 0u);
+        m = mir ? ~0u : 0u;
+    };
+    // float formats: two cross-shaped positions per thread; FP64 on an
+    // interior tile: chunk tid (row tid / (LC / 2), columns 2 (tid % (LC / 2))
+    // and the next)
+    uint32_t la[2] = {0u, 0u}, lm[2] = {0u, 0u};
+    int ldst[2] = {0, 0};
+    T lsin[2] = {T(0), T(0)};
+    if constexpr (DMA) {
+        if (inner) {
+            if (tid < NCH) locate(tid / (LC / 2), 2 * (tid % (LC / 2)), la[0], lm[0]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < (2 * LT + NTHR - 1) / NTHR; ++i) {
+                const int d = NTHR * i + tid;
+                if (d < 2 * LT) {
+                    uint32_t a, m;
+                    locate((d >> 1) / LC, (d >> 1) % LC, a, m);
+                    dtab[d] = a + (uint32_t)(d & 1) * 4u;
+                }
+            }
+        }
+        if (tid < LR) {
+            const int js = s0 + tid;                  // sin table index of row s0 - 3 + tid
+            ssin[tid] = D.rows.sinv[js < nt + 2 * NGH ? js : nt + 2 * NGH - 1];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            int idx = tid + NTHR * j;
+            const bool used = idx < NLOAD;
+            if (!used) idx = 0;
+            int r, c;
+            if (idx < LR * TQ) {
+                r = idx / TQ;
+                c = idx % TQ + NGH;
+            } else {
+                const int e = idx - LR * TQ, e2 = e % (TS * NGH);
+                r = e2 / NGH + NGH;
+                c = (e < TS * NGH) ? e2 % NGH : TQ + NGH + e2 % NGH;
+            }
+            ldst[j] = used ? SL::at(r, c) : SL::DUMMY;
+            locate(r, c, la[j], lm[j]);
+            const int js = s0 + r;                    // sin table index of row s0 - 3 + r
+            lsin[j] = T(D.rows.sinv[js < nt + 2 * NGH ? js : nt + 2 * NGH - 1]);
+        }
     }
+    // FP64: population k into ring slot b straight from memory (lane i of a
+    // wave writes bytes size i .. size (i + 1) - 1 past the wave's base)
+    using lds_ptr = __attribute__((address_space(3))) void*;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    auto dma = [&](int k, int b) {
+        if constexpr (DMA) {
+            const uint32_t kb = (uint32_t)k * planeB;
+            if (inner) {
+                if (tid < NCH)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(tile + b * LT + 2 * 64 * wv), 16,
+                                                             la[0], kb, 0, 0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < (2 * LT + NTHR - 1) / NTHR; ++i) {
+                    const int d = NTHR * i + tid;            // dword d of the slot
+                    if (d < 2 * LT) {
+                        const uint32_t a = dtab[d], m = 0u - (a & 1u);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            rin, (lds_ptr)((char*)(tile + b * LT) + 4 * (NTHR * i + 64 * wv)), 4, (kb ^ m) + a, 0,
+                            0, 0);
+                    }
+                }
+            }
+        }
+    };
     auto gload = [&](int k, int j) -> T {
         return St::bld(rin, (((uint32_t)k * planeB) ^ lm[j]) + la[j], 0, (float)C.iscale[k]);
     };
@@ -741,18 +813,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     // the i-th population lives in slot i % 3 and is written to LDS at the end
     // of iteration i - 2, when the slot of iteration i - 3 has been read for
     // the last time.  Its global loads are issued PF iterations ahead, at the
-    // start of iteration i - PF, into the register pair nx[i % 2]: FP64 (5
-    // waves per SIMD) gives them two iterations to arrive, the float kernels
-    // (7 waves) one.
+    // start of iteration i - PF, into the register pair nx[i % 2]: the float
+    // kernels (7 waves) give them one iteration to arrive.  FP64 loads the
+    // i-th population straight into its slot after the barrier of iteration
+    // i - 3, the last that reads that slot; a barrier is a workgroup release,
+    // which waits for the wave's direct-to-LDS loads, so the population is in
+    // LDS for every wave after the barrier of iteration i - 1.
     auto ord = [](int i) { return NQ == 4 ? ROUND_ORDER[i] : i; };
-    constexpr int PF = sizeof(T) == 8 ? 3 : 2;
+    constexpr int PF = 2;
     T nx[2][2];
-    {
+    if constexpr (DMA) {
+        dma(ord(0), 0);
+        dma(ord(1), 1);
+        dma(ord(2), 2);
+        __builtin_amdgcn_s_waitcnt(0x0f70);           // vmcnt 0 (the barrier's release needs it too)
+    } else {
         const T a0 = gload(ord(0), 0), a1 = gload(ord(0), 1), b0 = gload(ord(1), 0), b1 = gload(ord(1), 1);
-        if constexpr (PF == 3) {
-            nx[0][0] = gload(ord(2), 0);
-            nx[0][1] = gload(ord(2), 1);
-        }
         lstore(ord(0), 0, a0, a1);
         lstore(ord(1), 1, b0, b1);
     }
@@ -766,8 +842,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
         // theta and phi speeds of this population (zero: no flux in that direction)
         const int st = vsgn(kt), sp = vsgn(kp);
         T gself = T(0), Ftself = T(0), Flself = T(0);
-        // global loads of the population PF iterations ahead
-        if (i + PF < NK) {
+        // global loads of the population PF iterations ahead (float formats)
+        if (!DMA && i + PF < NK) {
             nx[(i + PF) & 1][0] = gload(ord(i + PF), 0);
             nx[(i + PF) & 1][1] = gload(ord(i + PF), 1);
         }
@@ -777,8 +853,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
                 const int a = (m & 1 ? tbase1 : tbase0) + (m >> 1) * SL::RS2;
-                g[m] = tile[3 * a + tb];
-                h[m] = tileh[3 * a + tb];
+                g[m] = slot(tb, a);
+                if constexpr (DMA) {
+                    h[m] = ssin[ti + m] * g[m];
+                    // a rounded product, as the float formats' second ring holds:
+                    // kept out of multiply-add contraction with the differences
+                    // the candidates take of it
+                    asm("" : "+v"(h[m]));
+                } else {
+                    h[m] = tileh[3 * a + tb];
+                }
             }
             gself = g[3];                                // this thread's cell (row ti, column tc)
             T F;
@@ -796,13 +880,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
             fth[fb][tid] = F;
             Ftself = F;                                  // top face of this thread's cell
         } else {
-            gself = tile[3 * (tbase1 + SL::RS2) + tb];   // LDS row ti+3
+            gself = slot(tb, tbase1 + SL::RS2);          // LDS row ti+3
         }
         // phi flux of g (the speed multiplies the difference)
         if (sp != 0) {
             T g[6];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) g[m] = tile[3 * (pbase + m) + tb];
+            for (int m = 0; m < 6; ++m) g[m] = slot(tb, pbase + m);
             T F;
             if constexpr (!UPW) {
                 if (sp > 0)
@@ -817,7 +901,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
             Flself = F;                                  // left face of this thread's cell
             if (phas) fph[fb][pslot] = F;
         }
+        if constexpr (DMA) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt 0: population i + 1 in LDS
         __syncthreads();
+        // FP64: population i + 3 into the slot this iteration has finished reading
+        if (DMA && i + 3 < NK) dma(ord(i + 3), tb);
         if (cell) {
             const T gc = gself;
             // FP64 folds the BGK loss -g/tau in here; the float kernels form the
@@ -852,7 +939,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
                 jp = fma(nodev(kp), gc, jp);
             }
         }
-        if (i + 2 < NK) lstore(ord(i + 2), (i + 2) % 3, nx[i & 1][0], nx[i & 1][1]);
+        if (!DMA && i + 2 < NK) lstore(ord(i + 2), (i + 2) % 3, nx[i & 1][0], nx[i & 1][1]);
         // keep this population's register arithmetic in place: deferring it past
         // the following barriers would keep every population's inputs live at once
         if constexpr (NK == 16)
