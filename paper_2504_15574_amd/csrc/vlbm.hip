@@ -397,11 +397,12 @@ enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
 // Minimum waves per SIMD the register allocation must allow: 7 for the float
 // kernels (at most 72 VGPRs; the general WENO-5 variant keeps two values in
 // scratch across the population loop and still gains 3.7 % over 6 waves), 6
-// for FP64 (at most 80 VGPRs: its row factors in LDS, its populations loaded
-// straight into LDS with nothing in flight in registers; 24 KB of LDS per
-// workgroup, six per CU).
+// 5 for FP64 (at most 96 VGPRs: its row factors in LDS, its populations
+// loaded straight into LDS with nothing in flight in registers, 24 KB of LDS
+// per workgroup).  Six FP64 waves fit (80 VGPRs) with barriers that wait for
+// all direct loads, but the longer load overlap at five is faster.
 template <class T, int VAR>
-constexpr int stage_min_waves() { return sizeof(T) == 8 ? 6 : 7; }
+constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
 // The float formats of D2Q16 with the WENO-5 standard form on 15 x 16 tiles
 // run stage_tile_rounds (same bits as stage_tile).  FP64 stays on stage_tile:
 // the rounds kernel needs 128 VGPRs there (four waves per SIMD, with spills;
@@ -573,7 +574,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     constexpr bool DMA = sizeof(T) == 8;
     constexpr int LC = Tl::LC, LT = Tl::LT, NCH = LT / 2;
     static_assert(!DMA || (LC % 2 == 0 && NCH <= NTHR && (LT * sizeof(T)) % 16 == 0), "FP64 ring slots");
-    __shared__ T tile[DMA ? 3 * LT : 3 * SL::SIZE];      // g of one population, cross-shaped halo
+    // (FP64: three LDS objects, so that the compiler's bookkeeping of the loads
+    // in flight into one slot never orders the reads of another)
+    __shared__ T tile[DMA ? LT : 3 * SL::SIZE];          // g of one population, cross-shaped halo
+    __shared__ T tile1[DMA ? LT : 1];
+    __shared__ T tile2[DMA ? LT : 1];
+    auto slot_base = [&](int b) -> T* { return b == 0 ? tile : (b == 1 ? tile1 : tile2); };
     __shared__ T tileh[DMA ? 1 : 3 * SL::SIZE];          // sin(theta_j) g_j: theta flux function without its speed
     __shared__ T ssin[DMA ? LR : 1];                     // sin(theta) of the tile's rows (FP64)
     // FP64 on a tile with pole rows or a phi wrap: the byte offset of each
@@ -581,7 +587,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     // the only odd one: +1 marks the mirror), written and read by the thread
     // that loads that dword
     __shared__ uint32_t dtab[DMA ? 2 * LT : 1];
-    auto slot = [&](int b, int a) -> const T& { return DMA ? tile[b * LT + a] : tile[3 * a + b]; };
+    auto slot = [&](int b, int a) -> const T& { return DMA ? slot_base(b)[a] : tile[3 * a + b]; };
     __shared__ T fth[2][NFT];
     __shared__ T fph[2][NFP + 1];              // faces with phi index < TQ row-major, then the TS right faces
 
@@ -675,7 +681,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
             const uint32_t kb = (uint32_t)k * planeB;
             if (inner) {
                 if (tid < NCH)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(tile + b * LT + 2 * 64 * wv), 16,
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(slot_base(b) + 2 * 64 * wv), 16,
                                                              la[0], kb, 0, 0);
             } else {
 #pragma unroll
@@ -684,7 +690,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
                     if (d < 2 * LT) {
                         const uint32_t a = dtab[d], m = 0u - (a & 1u);
                         __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                            rin, (lds_ptr)((char*)(tile + b * LT) + 4 * (NTHR * i + 64 * wv)), 4, (kb ^ m) + a, 0,
+                            rin, (lds_ptr)((char*)slot_base(b) + 4 * (NTHR * i + 64 * wv)), 4, (kb ^ m) + a, 0,
                             0, 0);
                     }
                 }
@@ -816,9 +822,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     // start of iteration i - PF, into the register pair nx[i % 2]: the float
     // kernels (7 waves) give them one iteration to arrive.  FP64 loads the
     // i-th population straight into its slot after the barrier of iteration
-    // i - 3, the last that reads that slot; a barrier is a workgroup release,
-    // which waits for the wave's direct-to-LDS loads, so the population is in
-    // LDS for every wave after the barrier of iteration i - 1.
+    // i - 3, the last that reads that slot; it must be in LDS for every wave
+    // after the barrier of iteration i - 1, two iterations later.
     auto ord = [](int i) { return NQ == 4 ? ROUND_ORDER[i] : i; };
     constexpr int PF = 2;
     T nx[2][2];
@@ -901,8 +906,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
             Flself = F;                                  // left face of this thread's cell
             if (phas) fph[fb][pslot] = F;
         }
-        if constexpr (DMA) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt 0: population i + 1 in LDS
-        __syncthreads();
+        if constexpr (DMA) {
+            // a plain barrier (a __syncthreads() would wait for all of the
+            // wave's direct-to-LDS loads): this wave's LDS reads and face writes
+            // done (lgkmcnt 0), and of its direct loads only population i + 2's
+            // still outstanding (an interior tile issues one per population;
+            // a border tile waits for all); the empty asm statements keep the
+            // compiler from moving memory accesses across
+            asm volatile("" ::: "memory");
+            if (inner && i + 2 < NK) __builtin_amdgcn_s_waitcnt(0x0071);   // vmcnt 1, lgkmcnt 0
+            else __builtin_amdgcn_s_waitcnt(0x0070);                       // vmcnt 0, lgkmcnt 0
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+        } else {
+            __syncthreads();
+        }
         // FP64: population i + 3 into the slot this iteration has finished reading
         if (DMA && i + 3 < NK) dma(ord(i + 3), tb);
         if (cell) {
