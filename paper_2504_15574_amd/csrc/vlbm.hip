@@ -560,13 +560,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     using SL = SlotLayout<Tl, (int)sizeof(T)>;
     // FP64 fills its ring with direct-to-LDS loads (no registers hold the
     // populations in flight, no LDS writes place them): each slot is the full
-    // LR x LC rectangle, row-major (SlotLayout's 8-byte form), at slot b *
-    // LR LC; an interior tile takes it as chunks of two neighbouring values,
-    // one 16-byte load per thread landing at byte 16 tid of the slot, a tile
-    // with pole rows or a phi wrap in its halo (where neighbouring halo values
-    // need not be neighbours in memory) dword by dword, with addresses formed
-    // at issue.  The theta flux function sin(theta) g is formed at the read
-    // from a table of the tile's rows.  The float formats interleave the
+    // LR x LC rectangle, row-major (SlotLayout's 8-byte form), in an LDS
+    // object of its own; an interior tile takes it as chunks of two
+    // neighbouring values, one 16-byte load per thread landing at byte 16 tid
+    // of the slot, a tile with pole rows or a phi wrap in its halo (where
+    // neighbouring halo values need not be neighbours in memory) dword by
+    // dword, at offsets each thread formed for its dwords at the tile's start.
+    // The theta flux function sin(theta) g is formed at the read from a table
+    // of the tile's rows.  The float formats interleave the
     // three ring slots element by element (element i of slot b at 3 i + b): a
     // thread's stencil reads in any slot then sit at small constant offsets
     // from one base address, so no per-slot address arithmetic; they keep
@@ -574,8 +575,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     constexpr bool DMA = sizeof(T) == 8;
     constexpr int LC = Tl::LC, LT = Tl::LT, NCH = LT / 2;
     static_assert(!DMA || (LC % 2 == 0 && NCH <= NTHR && (LT * sizeof(T)) % 16 == 0), "FP64 ring slots");
-    // (FP64: three LDS objects, so that the compiler's bookkeeping of the loads
-    // in flight into one slot never orders the reads of another)
+    // (FP64: three LDS objects, so that the compiler's bookkeeping of the
+    // loads in flight into one slot does not hold up the reads of another)
     __shared__ T tile[DMA ? LT : 3 * SL::SIZE];          // g of one population, cross-shaped halo
     __shared__ T tile1[DMA ? LT : 1];
     __shared__ T tile2[DMA ? LT : 1];
