@@ -13,7 +13,11 @@ Convergence (eq. (l2_err)): the time-integrated relative error of each mode
 against its closed form on N_theta = 16 .. 512 grids.  Sound (Sec. IV.A,
 u_theta(0) = U0 (pi - theta) theta, dt = tau = 2e-5, U0 = 1e-5; integrated to
 t = 4 rather than 20 to keep the test short): WENO-5 close to fifth order,
-U3 third, and every Komissarov variant second ("at most two").  Shear (tau =
+U3 third, U1 first, and the Komissarov variants at most second (U1 first).
+U2 in the standard form is not among them: with the flux function
+reconstructed point by point (the reading that gives WENO-5 its fifth order)
+it grows unstable from the pole rows on grids up to N_theta = 128, in the CPU
+oracle as in the kernels.  Shear (tau =
 1e-3, dt = 1e-4, t = 20, initial layer as above): the WENO-5 order rises with
 the resolution towards the paper's four to five (measured 3.6 - 4.5 from 256
 to 512).  Measured values are printed.
@@ -90,8 +94,11 @@ SOUND_NS = [16, 32, 64, 128, 256, 512]
 @pytest.mark.parametrize("scheme,komissarov,window,lo,hi", [
     ("weno5", False, (1, 4), 4.0, 5.6),     # fifth order (Sec. IV.A)
     ("u3", False, (1, 4), 2.6, 3.6),        # third
+    ("u1", False, (1, 4), 0.8, 1.3),        # first
     ("u3", True, (3, 5), 1.8, 2.3),         # Komissarov form: at most two
     ("weno5", True, (3, 5), 1.8, 2.3),
+    ("u2", True, (3, 5), 1.8, 2.3),
+    ("u1", True, (3, 5), 0.6, 1.2),         # first (modes 2, 3 still pre-asymptotic)
 ])
 def test_sound_wave_convergence_orders(scheme, komissarov, window, lo, hi):
     tau, dt, modes = 2e-5, 2e-5, [1, 2, 3]
@@ -105,7 +112,9 @@ def test_sound_wave_convergence_orders(scheme, komissarov, window, lo, hi):
     print("  orders (rows: successive refinements, columns: n = 1, 2, 3):\n" + np.array2string(o, precision=2))
     mean = o[window[0]:window[1]].mean(axis=0)
     assert np.all(mean > lo) and np.all(mean < hi), mean
-    assert errs[SOUND_NS[-1]][0] < errs[SOUND_NS[0]][0] * 1e-2
+    # the error falls with the resolution: 100 x from N_theta = 16 to 512 for
+    # second order and above, 10 x for first order (32 x finer)
+    assert errs[SOUND_NS[-1]][0] < errs[SOUND_NS[0]][0] * (1e-2 if lo >= 1.5 else 1e-1)
 
 
 def test_shear_wave_convergence_order():
