@@ -111,6 +111,27 @@ def test_graph_replays_match_eager_steps():
         s.close()
 
 
+def test_graph_replays_of_the_direct_to_lds_form_match_eager_steps():
+    # A graph of one FP32 run of 512 x 1024 (2240 15 x 16 tiles) records the
+    # rounds kernel's direct-to-LDS form; its replays, with eager work between
+    # them, must equal eager stepping of the same run (which takes that form too).
+    from paper_2504_15574_amd import Ensemble
+    g = _runs("f32", [(512, 1024)], seed=6)
+    e = _runs("f32", [(512, 1024)], seed=6)
+    other = _runs("f32", [(24, 48)], seed=7)[0]
+    ens_g = Ensemble(g)
+    ens_g.capture(3)
+    for rep in range(3):
+        ens_g.replay()
+        e[0].step(3)
+        other.step(1)
+        _ = g[0].moments()
+        assert np.array_equal(g[0].populations(), e[0].populations()), f"replay {rep}"
+    ens_g.release()
+    for s in g + e + [other]:
+        s.close()
+
+
 def test_batch_argument_errors():
     from paper_2504_15574_amd import VlbmError, vlbm_step_batch
     a = _runs("f32", [(16, 32)], seed=5)[0]
