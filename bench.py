@@ -287,48 +287,76 @@ def cpu_baseline(state, threads):
     return out
 
 
+def _scheme_mlups(n_theta, n_phi, tau, state, steps, **kw):
+    """MLUPS of one Solver configuration: `steps` timed steps after 2 warm-up
+    steps, timed with HIP events on the run's stream; also whether it stayed
+    finite."""
+    import torch
+    from paper_2504_15574_amd import Solver
+    sol = Solver(n_theta, n_phi, tau, **kw)
+    sol.init_fields(*state)
+    sol.step(2)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sol.stream)
+    sol.step(steps)
+    e1.record(sol.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ok = sol.diagnostics(raise_unstable=False)[4] == 0
+    sol.close()
+    return {"mlups": round(n_theta * n_phi / (ms * 1e-3) / 1e6, 1), "finite": bool(ok)}
+
+
+SCHEMES = [(sc, kom) for sc in ("u1", "u2", "u3", "weno5") for kom in (False, True)]
+
+
+def _scheme_key(scheme, kom):
+    return f"{scheme}{'+komissarov' if kom else ''}"
+
+
 def run_schemes(state, steps):
     """Cost of the advection schemes on the benchmark grid: MLUPS of U1, U2, U3
     and WENO-5, each in the standard and the Komissarov form, FP32 and FP64
     deviation store, and of the D2Q9 model (Q = 3) with WENO-5; `steps` timed
     steps after 2 warm-up steps."""
-    import torch
-    from paper_2504_15574_amd import Solver
     out = {}
     for storage in ("f32", "f64"):
-        for scheme in ("u1", "u2", "u3", "weno5"):
-            for kom in (False, True):
-                sol = Solver(N_THETA, N_PHI, TAU, storage=storage, scheme=scheme, komissarov=kom)
-                sol.init_fields(*state)
-                sol.step(2)
-                torch.cuda.synchronize()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(sol.stream)
-                sol.step(steps)
-                e1.record(sol.stream)
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / steps
-                ok = sol.diagnostics(raise_unstable=False)[4] == 0
-                sol.close()
-                out[f"{storage}/{scheme}{'+komissarov' if kom else ''}"] = {
-                    "mlups": round(N_THETA * N_PHI / (ms * 1e-3) / 1e6, 1), "finite": bool(ok)}
+        for scheme, kom in SCHEMES:
+            out[f"{storage}/{_scheme_key(scheme, kom)}"] = _scheme_mlups(
+                N_THETA, N_PHI, TAU, state, steps, storage=storage, scheme=scheme, komissarov=kom)
     for storage in ("f32", "f64"):
-        sol = Solver(N_THETA, N_PHI, TAU, storage=storage, q=3)
-        sol.init_fields(*state)
-        sol.step(2)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(sol.stream)
-        sol.step(steps)
-        e1.record(sol.stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        ok = sol.diagnostics(raise_unstable=False)[4] == 0
-        sol.close()
-        out[f"{storage}/d2q9-weno5"] = {"mlups": round(N_THETA * N_PHI / (ms * 1e-3) / 1e6, 1),
-                                        "finite": bool(ok)}
+        out[f"{storage}/d2q9-weno5"] = _scheme_mlups(N_THETA, N_PHI, TAU, state, steps,
+                                                     storage=storage, q=3)
+    return out
+
+
+def run_schemes_sound(steps, n=1024):
+    """The scheme comparison of the paper's performance section (Sec. V): the
+    sound wave u_theta = U0 theta (pi - theta), U0 = 1e-5, on a fully 2-D
+    n x n grid, FP64, every advection scheme in the standard and the
+    Komissarov form (FP32 deviation store alongside).  Besides the MLUPS the
+    block gives the step-time ratios the paper states in words: WENO-5 over
+    U1, U3 over U1 and each Komissarov form over its standard form."""
+    import workloads as W
+    state = W.sound_wave_parabolic(n, n, U0=1e-5)
+    tau = 1e-3
+    out = {"workload": f"sound wave u_theta = 1e-5 theta (pi - theta), {n}x{n} cells, "
+                       f"D2Q16, tau = {tau}", "mlups": {}}
+    for storage in ("f64", "f32"):
+        for scheme, kom in SCHEMES:
+            out["mlups"][f"{storage}/{_scheme_key(scheme, kom)}"] = _scheme_mlups(
+                n, n, tau, state, steps, storage=storage, scheme=scheme, komissarov=kom)
+    m = {k: v["mlups"] for k, v in out["mlups"].items()}
+    ratios = {}
+    for storage in ("f64", "f32"):
+        ratios[f"{storage}/weno5_over_u1"] = round(m[f"{storage}/u1"] / m[f"{storage}/weno5"], 3)
+        ratios[f"{storage}/u3_over_u1"] = round(m[f"{storage}/u1"] / m[f"{storage}/u3"], 3)
+        for scheme, _ in SCHEMES[::2]:
+            ratios[f"{storage}/{scheme}+komissarov_over_{scheme}"] = round(
+                m[f"{storage}/{scheme}"] / m[f"{storage}/{scheme}+komissarov"], 3)
+    out["step_time_ratios"] = ratios
     return out
 
 
@@ -380,6 +408,7 @@ def main():
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the advection-scheme cost comparison (U1/U2/U3/WENO-5, Komissarov)")
     ap.add_argument("--scheme-steps", type=int, default=100)
+    ap.add_argument("--scheme-steps-sound", type=int, default=200)
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the learned-closure experiment (training and evaluation, ~20 s)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -485,6 +514,10 @@ def main():
         print("[bench] advection schemes ...", file=sys.stderr, flush=True)
         out["schemes"] = run_schemes(state, args.scheme_steps)
         print(f"[bench] schemes: {out['schemes']}", file=sys.stderr, flush=True)
+        print("[bench] advection schemes, 1024x1024 sound wave ...", file=sys.stderr, flush=True)
+        out["schemes_sound_1024"] = run_schemes_sound(args.scheme_steps_sound)
+        print(f"[bench] schemes_sound_1024: {out['schemes_sound_1024']}", file=sys.stderr,
+              flush=True)
 
     if not args.no_closure:
         print("[bench] learned closure: fine data, training, evaluation ...", file=sys.stderr,

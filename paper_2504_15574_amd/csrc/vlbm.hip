@@ -396,7 +396,7 @@ __host__ __device__ inline int n_tiles(int nt, int np, int shape) {
 enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
 // Minimum waves per SIMD the register allocation must allow: 7 for the float
 // kernels (at most 72 VGPRs; the general WENO-5 variant keeps two values in
-// scratch across the population loop and still gains 3.7 % over 6 waves), 6
+// scratch across the population loop and still gains 3.7 % over 6 waves),
 // 5 for FP64 (at most 96 VGPRs: its row factors in LDS, its populations
 // loaded straight into LDS with nothing in flight in registers, 24 KB of LDS
 // per workgroup).  Six FP64 waves fit (80 VGPRs) with barriers that wait for
@@ -422,10 +422,30 @@ constexpr int launch_min_waves() {
 // holds g + dt L without the equilibrium (FP64) or dt L without it (float
 // formats, which keep the cell's stage input in gk); FP64 brings the moments
 // of its running sums (drho, jt, jp), the float formats form them from gk.
+// Stages 2 and 3 combine with the step's input g_n (coefficient a != 0).  The
+// tile functions issue its sixteen loads for their cell together, once their
+// last population's fluxes are in LDS, so that the memory latency is paid once
+// per cell and overlaps the last accumulation instead of stalling every store.
+template <class St, int NQ>
+__device__ __forceinline__ void load_gn(const RunDesc& D, const ConstsT<typename St::T>& C, int cs, int cq,
+                                        typename St::T (&gnv)[NQ * NQ]) {
+    constexpr int NK = NQ * NQ;
+    using T = typename St::T;
+    constexpr int B = St::B;
+    if (uni<T>(D, U_A) != T(0)) {
+        const uint32_t planeB = (uint32_t)D.nt * (uint32_t)D.np * B;
+        const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
+        const uint32_t cvo = ((uint32_t)cs * (uint32_t)D.np + (uint32_t)cq) * B;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) gnv[k] = St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+    }
+}
+
 template <class St, int NQ>
 __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<typename St::T>& C,
                                                typename St::T (&acc)[NQ * NQ],
                                                const typename St::T (&gk)[NQ * NQ],
+                                               const typename St::T (&gnv)[NQ * NQ],
                                                typename St::T drho, typename St::T jt,
                                                typename St::T jp, int cs, int cq, uint32_t ctr) {
     constexpr int NK = NQ * NQ;
@@ -484,7 +504,6 @@ __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<t
         return (vsgn(kt) < 0 ? -a : a) + (vsgn(kp) < 0 ? -b : b);
     };
     const T ca = uni<T>(D, U_A), cb = uni<T>(D, U_B);
-    const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
     const rsrc_t rout = make_rsrc(D.out, NK * planeB);
     const uint32_t cvo = ((uint32_t)cs * (uint32_t)np + (uint32_t)cq) * B;
     // float kernels.  A reduced-precision store adds, every stage, nearly the
@@ -517,14 +536,14 @@ __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<t
             // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
             const T y = fma(dti * C.wk[k], t, acc[k]);
             T o = cb * y;
-            if (ca != T(0)) o += ca * St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]);
+            if (ca != T(0)) o += ca * gnv[k];
             St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
         } else {
             const T g = gk[k];
             // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
             // kernels' row factors, rest table and dt/tau come multiplied by b
             T d = fma(dti, fma(C.wk[k], t, -g), acc[k]);
-            if (ca != T(0)) d += ca * (St::bld(rgn, cvo, (uint32_t)k * planeB, (float)C.iscale[k]) - g);
+            if (ca != T(0)) d += ca * (gnv[k] - g);
             const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
             St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
         }
@@ -782,6 +801,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     // the sums start from the rest state's dt L of the cell's row
     T acc[NK];
     T gk[NK];   // the cell's stage input, kept for the float epilogue
+    T gnv[NK];  // the step's input g_n (stages 2 and 3)
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         acc[k] = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
@@ -924,6 +944,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
         }
         // FP64: population i + 3 into the slot this iteration has finished reading
         if (DMA && i + 3 < NK) dma(ord(i + 3), tb);
+        if (i == NK - 1 && valid) load_gn<St, NQ>(D, C, cs, cq, gnv);
         if (cell) {
             const T gc = gself;
             // FP64 folds the BGK loss -g/tau in here; the float kernels form the
@@ -973,7 +994,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     }
 
     if (!valid) return;
-    stage_epilogue<St, NQ>(D, C, acc, gk, drho, jt, jp, cs, cq, ctr);
+    stage_epilogue<St, NQ>(D, C, acc, gk, gnv, drho, jt, jp, cs, cq, ctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1110,6 +1131,7 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     const uint32_t rvo = (uint32_t)csc * (uint32_t)sizeof(T);
     T acc[NK];
     T gk[NK];
+    T gnv[NK];  // the step's input g_n (stages 2 and 3)
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         acc[k] = St::rload(rrest, rvo, (uint32_t)(k * nt) * (uint32_t)sizeof(T));
@@ -1284,6 +1306,7 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
             put();
             if (r < 2) issue(r + 2);
         }
+        if (r == 3 && valid) load_gn<St, NQ>(D, C, cs, cq, gnv);
         // -- the cells accumulate the round's populations in order
         if (cell) {
 #pragma unroll
@@ -1326,7 +1349,7 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
         }
     }
     if (!valid) return;
-    stage_epilogue<St, NQ>(D, C, acc, gk, drho, jt, jp, cs, cq, ctr);
+    stage_epilogue<St, NQ>(D, C, acc, gk, gnv, drho, jt, jp, cs, cq, ctr);
 }
 
 // the run of global tile tg: the largest run with tile_start[run] <= tg
