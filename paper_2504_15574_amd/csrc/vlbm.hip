@@ -114,6 +114,8 @@ struct FaceRowK {       // theta interface i (between rows i-1 and i)
 };
 // SSP-RK3 (Sec. III.G): stage i writes a_i g_n + b_i (g_in + dt L(g_in))
 constexpr double RK_A[3] = {0.0, 0.75, 1.0 / 3.0}, RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
+// (per-stage launches compile stage 1 without g_n and stages 2, 3 with it)
+static_assert(RK_A[0] == 0.0 && RK_A[1] != 0.0 && RK_A[2] != 0.0, "only stage 1 skips g_n");
 // run constants in both arithmetic types (uniform per workgroup: scalar loads)
 enum { U_DTI, U_EPSK, U_OMDTI, U_RHO0, U_A, U_B, U_N };
 
@@ -426,13 +428,17 @@ constexpr int launch_min_waves() {
 // tile functions issue its sixteen loads for their cell together, once their
 // last population's fluxes are in LDS, so that the memory latency is paid once
 // per cell and overlaps the last accumulation instead of stalling every store.
-template <class St, int NQ>
+// GN: which stages a compiled copy serves.  Per-stage launches take a copy
+// without g_n (stage 1) or one that always combines with it (stages 2, 3);
+// the persistent kernel, which runs all three stages, tests a at run time.
+enum { GN_NONE = 0, GN_LOAD = 1, GN_RUNTIME = 2 };
+template <class St, int NQ, int GN>
 __device__ __forceinline__ void load_gn(const RunDesc& D, const ConstsT<typename St::T>& C, int cs, int cq,
                                         typename St::T (&gnv)[NQ * NQ]) {
     constexpr int NK = NQ * NQ;
     using T = typename St::T;
     constexpr int B = St::B;
-    if (uni<T>(D, U_A) != T(0)) {
+    if (GN == GN_LOAD || (GN == GN_RUNTIME && uni<T>(D, U_A) != T(0))) {
         const uint32_t planeB = (uint32_t)D.nt * (uint32_t)D.np * B;
         const rsrc_t rgn = make_rsrc(D.gn, NK * planeB);
         const uint32_t cvo = ((uint32_t)cs * (uint32_t)D.np + (uint32_t)cq) * B;
@@ -441,7 +447,7 @@ __device__ __forceinline__ void load_gn(const RunDesc& D, const ConstsT<typename
     }
 }
 
-template <class St, int NQ>
+template <class St, int NQ, int GN>
 __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<typename St::T>& C,
                                                typename St::T (&acc)[NQ * NQ],
                                                const typename St::T (&gk)[NQ * NQ],
@@ -530,45 +536,49 @@ __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<t
         hsh ^= hsh >> 15; hsh *= 0x846ca68bu;
         hsh ^= hsh >> 16;
     }
-    // store population k, whose equilibrium deviation is w_k (drho + rho P)
-    auto finish = [&](int k, T t) {
-        if constexpr (sizeof(T) == 8) {
-            // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
-            const T y = fma(dti * C.wk[k], t, acc[k]);
-            T o = cb * y;
-            if (ca != T(0)) o += ca * gnv[k];
-            St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
-        } else {
-            const T g = gk[k];
-            // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
-            // kernels' row factors, rest table and dt/tau come multiplied by b
-            T d = fma(dti, fma(C.wk[k], t, -g), acc[k]);
-            if (ca != T(0)) d += ca * (gnv[k] - g);
-            const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
-            St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
-        }
-    };
-    // drho + rho P for each population and its mirror, stored pair by pair
+    {
+        // combine with g_n: always (GN_LOAD), never (GN_NONE) or where a != 0
+        const bool CB = GN == GN_LOAD || (GN == GN_RUNTIME && ca != T(0));
+        // store population k, whose equilibrium deviation is w_k (drho + rho P)
+        auto finish = [&](int k, T t) {
+            if constexpr (sizeof(T) == 8) {
+                // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
+                const T y = fma(dti * C.wk[k], t, acc[k]);
+                T o = cb * y;
+                if (CB) o += ca * gnv[k];
+                St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
+            } else {
+                const T g = gk[k];
+                // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
+                // kernels' row factors, rest table and dt/tau come multiplied by b
+                T d = fma(dti, fma(C.wk[k], t, -g), acc[k]);
+                if (CB) d += ca * (gnv[k] - g);
+                const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
+                St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
+            }
+        };
+        // drho + rho P for each population and its mirror, stored pair by pair
 #pragma unroll
-    for (int k = 0; 2 * k < NK - 1; ++k) {
-        const T xi = xi_of(k);
-        const T x2 = xi * xi;
-        const T base = fma(rho, fma(T(0.5), x2, ev0), drho);
-        T od;
-        if constexpr (NQ == 4) od = fma(xi, fma(x2, T(1.0 / 6.0), cu), xi);
-        else od = fma(xi, C.eq_e1, xi);
-        const T ro = rho * od;
-        finish(k, base + ro);
-        finish(NK - 1 - k, base - ro);
+        for (int k = 0; 2 * k < NK - 1; ++k) {
+            const T xi = xi_of(k);
+            const T x2 = xi * xi;
+            const T base = fma(rho, fma(T(0.5), x2, ev0), drho);
+            T od;
+            if constexpr (NQ == 4) od = fma(xi, fma(x2, T(1.0 / 6.0), cu), xi);
+            else od = fma(xi, C.eq_e1, xi);
+            const T ro = rho * od;
+            finish(k, base + ro);
+            finish(NK - 1 - k, base - ro);
+        }
+        if constexpr (NK & 1) finish(NK / 2, fma(rho, ev0, drho));     // xi = 0
     }
-    if constexpr (NK & 1) finish(NK / 2, fma(rho, ev0, drho));     // xi = 0
 }
 
 // One tile of one run at one RK stage: tile t of the run described by D, whose
 // reduced-precision stores take the dither phase of step ctr.  Every thread of
 // the workgroup calls it; it ends after its last barrier (threads without a
 // cell return before the epilogue).
-template <class St, class Tl, int VAR, int NQ>
+template <class St, class Tl, int VAR, int NQ, int GN>
 __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D, int t, uint32_t ctr) {
     constexpr bool GEN = VAR != VAR_WENO, UPW = VAR == VAR_UPWIND;
     constexpr int NK = NQ * NQ;
@@ -944,7 +954,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
         }
         // FP64: population i + 3 into the slot this iteration has finished reading
         if (DMA && i + 3 < NK) dma(ord(i + 3), tb);
-        if (i == NK - 1 && valid) load_gn<St, NQ>(D, C, cs, cq, gnv);
+        if (i == NK - 1 && valid) load_gn<St, NQ, GN>(D, C, cs, cq, gnv);
         if (cell) {
             const T gc = gself;
             // FP64 folds the BGK loss -g/tau in here; the float kernels form the
@@ -994,7 +1004,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
     }
 
     if (!valid) return;
-    stage_epilogue<St, NQ>(D, C, acc, gk, gnv, drho, jt, jp, cs, cq, ctr);
+    stage_epilogue<St, NQ, GN>(D, C, acc, gk, gnv, drho, jt, jp, cs, cq, ctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,7 +1035,7 @@ __device__ __forceinline__ T scalar_load(const T* p, int i) {
     return ((const __attribute__((address_space(4))) T*)p)[i];
 }
 
-template <class St, bool LDSDMA>
+template <class St, bool LDSDMA, int GN>
 __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunDesc& D, int t, uint32_t ctr) {
     using Tl = Tile15x16;
     constexpr int NQ = 4, NK = 16;
@@ -1306,7 +1316,7 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
             put();
             if (r < 2) issue(r + 2);
         }
-        if (r == 3 && valid) load_gn<St, NQ>(D, C, cs, cq, gnv);
+        if (r == 3 && valid) load_gn<St, NQ, GN>(D, C, cs, cq, gnv);
         // -- the cells accumulate the round's populations in order
         if (cell) {
 #pragma unroll
@@ -1349,7 +1359,7 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
         }
     }
     if (!valid) return;
-    stage_epilogue<St, NQ>(D, C, acc, gk, gnv, drho, jt, jp, cs, cq, ctr);
+    stage_epilogue<St, NQ, GN>(D, C, acc, gk, gnv, drho, jt, jp, cs, cq, ctr);
 }
 
 // the run of global tile tg: the largest run with tile_start[run] <= tg
@@ -1370,7 +1380,7 @@ __device__ __forceinline__ int run_of(const StageArgs& A, int tg) {
 // its run from the kernel arguments; a batched one looks up the run of its
 // tile (uniform per workgroup).  LDSDMA: the rounds kernel's direct-to-LDS
 // form (FP32).
-template <class St, bool BATCH, class Tl, int VAR, int NQ, bool LDSDMA = false>
+template <class St, bool BATCH, class Tl, int VAR, int NQ, bool LDSDMA, int GN>
 __global__ __launch_bounds__(NTHR, (launch_min_waves<St, Tl, VAR, NQ, LDSDMA>())) void stage_kernel(StageArgs A) {
     const int nall = A.tile_start[A.nruns];
     const int per = (nall + 7) / 8;
@@ -1380,9 +1390,9 @@ __global__ __launch_bounds__(NTHR, (launch_min_waves<St, Tl, VAR, NQ, LDSDMA>())
     const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
     const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr;
     if constexpr (uses_rounds<typename St::T, Tl, VAR, NQ>())
-        stage_tile_rounds<St, LDSDMA>(A, D, tg - A.tile_start[run], ctr);
+        stage_tile_rounds<St, LDSDMA, GN>(A, D, tg - A.tile_start[run], ctr);
     else
-        stage_tile<St, Tl, VAR, NQ>(A, D, tg - A.tile_start[run], ctr);
+        stage_tile<St, Tl, VAR, NQ, GN>(A, D, tg - A.tile_start[run], ctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1496,7 +1506,7 @@ __global__ __launch_bounds__(NTHR, (stage_min_waves<typename St::T, VAR_WENO>())
                     const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr + (uint32_t)step;
                     // stage_tile even where per-stage launches take stage_tile_rounds
                     // (same bits): inside this loop the rounds kernel spills
-                    stage_tile<St, Tl, VAR_WENO, 4>(A, D, tg - A.tile_start[run], ctr);
+                    stage_tile<St, Tl, VAR_WENO, 4, GN_RUNTIME>(A, D, tg - A.tile_start[run], ctr);
                 }
                 __syncthreads();                       // the tile's LDS is free again
             }
@@ -2231,15 +2241,22 @@ vlbm_status launch_group(vlbm_ctx* const* xs, int m, int stage, hipStream_t stre
         fill_descs(xs[0], d);
         A.run0 = d[stage - 1];
     }
+    // stage 1 runs the copy without the step input g_n, stages 2 and 3 the
+    // copy that combines with it
     auto go = [&](auto batch, auto tl) {
         constexpr bool BT = decltype(batch)::value;
         using TL = decltype(tl);
-        if constexpr (VAR == VAR_WENO) {
-            hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR_WENO, 4>), grid, dim3(NTHR), 0, stream, A);
-        } else {
-            if (d2q9) hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR, 3>), grid, dim3(NTHR), 0, stream, A);
-            else hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR, 4>), grid, dim3(NTHR), 0, stream, A);
-        }
+        auto launch = [&](auto gn) {
+            constexpr int GN = decltype(gn)::value;
+            if constexpr (VAR == VAR_WENO) {
+                hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR_WENO, 4, false, GN>), grid, dim3(NTHR), 0, stream, A);
+            } else {
+                if (d2q9) hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR, 3, false, GN>), grid, dim3(NTHR), 0, stream, A);
+                else hipLaunchKernelGGL((stage_kernel<St, BT, TL, VAR, 4, false, GN>), grid, dim3(NTHR), 0, stream, A);
+            }
+        };
+        if (stage == 1) launch(std::integral_constant<int, GN_NONE>{});
+        else launch(std::integral_constant<int, GN_LOAD>{});
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -2250,7 +2267,10 @@ vlbm_status launch_group(vlbm_ctx* const* xs, int m, int stage, hipStream_t stre
     constexpr int DMA_MIN_TILES = 2048;
     if constexpr (std::is_same<St, StF32>::value && VAR == VAR_WENO) {
         if (m == 1 && !wide && nb >= DMA_MIN_TILES) {
-            hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR_WENO, 4, true>), grid, dim3(NTHR), 0, stream, A);
+            if (stage == 1)
+                hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR_WENO, 4, true, GN_NONE>), grid, dim3(NTHR), 0, stream, A);
+            else
+                hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR_WENO, 4, true, GN_LOAD>), grid, dim3(NTHR), 0, stream, A);
             return launch_check();
         }
     }
