@@ -457,6 +457,11 @@ __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<t
                                                typename St::T (&gnv)[NQ * NQ],
                                                typename St::T drho, typename St::T jt,
                                                typename St::T jp, int cs, int cq, uint32_t ctr) {
+    // No implicit multiply-add contraction here: every fused operation is
+    // written as fma(), so each value rounds the same way in every compiled
+    // copy (the compiler's contraction choices follow the block structure,
+    // which differs between the per-stage and the persistent kernels).
+#pragma clang fp contract(off)
     constexpr int NK = NQ * NQ;
     using T = typename St::T;
     constexpr int B = St::B;
@@ -501,7 +506,7 @@ __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<t
     const T rho = rho0 + drho;
     const T irho = rcp_nr(rho);
     const T ut = jt * irho, up = jp * irho;
-    const T u2 = ut * ut + up * up;
+    const T u2 = fma(up, up, ut * ut);
     const T ev0 = C.eq_hb * u2;
     const T cu = fma(-C.eq_g6, u2, C.eq_e1);
     // v_o u and v_i u (theta and phi components); the inner node is 0 for Q = 3
@@ -553,14 +558,14 @@ __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<t
                 // FP64: y = g + dt L was accumulated directly; out = a g_n + b y
                 const T y = fma(dti * C.wk[k], t, acc[k]);
                 T o = cb * y;
-                if (GN == GN_LOAD || (GN == GN_RUNTIME && ca != T(0))) o += ca * gn_of(k);
+                if (GN == GN_LOAD || (GN == GN_RUNTIME && ca != T(0))) o = fma(ca, gn_of(k), o);
                 St::bst(rout, cvo, (uint32_t)k * planeB, o, (float)C.scale[k]);
             } else {
                 const T g = gk[k];
                 // out = a g_n + b (g + inc) = g + [a (g_n - g) + b inc]; the float
                 // kernels' row factors, rest table and dt/tau come multiplied by b
                 T d = fma(dti, fma(C.wk[k], t, -g), acc[k]);
-                if (GN == GN_LOAD || (GN == GN_RUNTIME && ca != T(0))) d += ca * (gn_of(k) - g);
+                if (GN == GN_LOAD || (GN == GN_RUNTIME && ca != T(0))) d = fma(ca, gn_of(k) - g, d);
                 const float x = (float)(int32_t)(hsh + (uint32_t)k * 0x9E3779B9u);
                 St::bst_dither(rout, cvo, (uint32_t)k * planeB, g, d, x, (float)C.scale[k]);
             }
@@ -574,9 +579,8 @@ __device__ __forceinline__ void stage_epilogue(const RunDesc& D, const ConstsT<t
             T od;
             if constexpr (NQ == 4) od = fma(xi, fma(x2, T(1.0 / 6.0), cu), xi);
             else od = fma(xi, C.eq_e1, xi);
-            const T ro = rho * od;
-            finish(k, base + ro);
-            finish(NK - 1 - k, base - ro);
+            finish(k, fma(rho, od, base));
+            finish(NK - 1 - k, fma(-rho, od, base));
         }
         if constexpr (NK & 1) finish(NK / 2, fma(rho, ev0, drho));     // xi = 0
     }
