@@ -1186,17 +1186,25 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     T nx[4][2];
     auto issue = [&](int r) {
         if constexpr (DMA) {
+            // an interior tile passes the population's offset as the scalar
+            // offset (no per-load address arithmetic); a tile with pole rows
+            // or a phi wrap folds it into each lane's offset
+            auto issue_as = [&](auto interior) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const uint32_t kb = (uint32_t)ROUND_ORDER[4 * r + p] * planeB;
+                for (int p = 0; p < 4; ++p) {
+                    const uint32_t kb = (uint32_t)ROUND_ORDER[4 * r + p] * planeB;
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    if (NTHR * j + tid < NDW)
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                            rin,
-                            (__attribute__((address_space(3))) void*)(tile + ((r & 1) * 4 + p) * PSZ + NTHR * j + 64 * w),
-                            4, (kb ^ lm[j]) + la[j], 0, 0, 0);
-            }
+                    for (int j = 0; j < 2; ++j)
+                        if (NTHR * j + tid < NDW)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                rin,
+                                (__attribute__((address_space(3))) void*)(tile + ((r & 1) * 4 + p) * PSZ + NTHR * j + 64 * w),
+                                4, decltype(interior)::value ? la[j] : (kb ^ lm[j]) + la[j],
+                                decltype(interior)::value ? kb : 0u, 0, 0);
+                }
+            };
+            if (inner) issue_as(std::true_type{});
+            else issue_as(std::false_type{});
         } else {
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
