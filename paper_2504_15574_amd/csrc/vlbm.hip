@@ -267,15 +267,14 @@ template <class T> __device__ __forceinline__ T rcp_nr(T x) {
 }
 
 // REST also marks the theta flux (h = sin th g); without it h is g itself
-// (phi), and the float kernels take the candidate differences from the
-// indicators' second differences: 3 (h2 - h1) + (h0 - h3) = a1 - a2,
-// 3 (h3 - h2) + (h1 - h4) = a2 - a3, 5 h2 + 2 h3 - h1 = 6 h2 + 2 D2 + D1 (one
-// instruction fewer each for A and B; FP64 keeps the direct form, whose
-// register allocation does not spill).
+// (phi), and the candidate differences come from the indicators' second
+// differences: 3 (h2 - h1) + (h0 - h3) = a1 - a2, 3 (h3 - h2) + (h1 - h4) =
+// a2 - a3, 5 h2 + 2 h3 - h1 = 6 h2 + 2 D2 + D1 (one instruction fewer each for
+// A and B).
 template <class T, bool REST>
 __device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T g2, T g3, T g4,
                                      T epsk, T wr, T c1, T c3) {
-    constexpr bool DIRECT = REST || sizeof(T) == 8;
+    constexpr bool DIRECT = REST;
     T G2, A, B;
     if constexpr (DIRECT) {
         G2 = fma(T(5), h2, fma(T(2), h3, -h1));                 // 6 F2
