@@ -306,11 +306,12 @@ __device__ __forceinline__ T weno5x6(T h0, T h1, T h2, T h3, T h4, T g0, T g1, T
 // Upwind fluxes U1, U2, U3 of eq. (fluxes_U1-3) from the stencil points in
 // upwind order (a = s-1, b = s, c = s+1 for a positive velocity; the mirror
 // s+2, s+1, s for a negative one).
+// (written with explicit fma, so that every kernel rounds them the same way)
 template <class T>
 __device__ __forceinline__ T upwind(int scheme, T a, T b, T c) {
     if (scheme == VLBM_ADV_U1) return b;
-    if (scheme == VLBM_ADV_U2) return T(1.5) * b - T(0.5) * a;
-    return c * T(1.0 / 3.0) + b * T(5.0 / 6.0) - a * T(1.0 / 6.0);
+    if (scheme == VLBM_ADV_U2) return fma(T(1.5), b, T(-0.5) * a);
+    return fma(T(1.0 / 3.0), c, fma(T(5.0 / 6.0), b, T(-1.0 / 6.0) * a));
 }
 
 template <class T> __device__ __forceinline__ const ConstsT<T>& consts_of(const StageArgs& A);
@@ -404,12 +405,15 @@ enum { VAR_WENO = 0, VAR_WENO_GEN = 1, VAR_UPWIND = 2 };
 // all direct loads, but the longer load overlap at five is faster.
 template <class T, int VAR>
 constexpr int stage_min_waves() { return sizeof(T) == 8 ? 5 : 7; }
-// The float formats of D2Q16 with the WENO-5 standard form on 15 x 16 tiles
-// run stage_tile_rounds (same bits as stage_tile).  FP64 stays on stage_tile:
+// The float formats of D2Q16 with the WENO-5 standard form or an upwind
+// scheme (either theta form) on 15 x 16 tiles run stage_tile_rounds (same
+// bits as stage_tile).  FP64 stays on stage_tile:
 // the rounds kernel needs 128 VGPRs there (four waves per SIMD, with spills;
 // three waves without) and ran 25 % (8 %) slower than stage_tile at five.
 template <class T, class Tl, int VAR, int NQ>
-constexpr bool uses_rounds() { return sizeof(T) != 8 && Tl::TS == 15 && VAR == VAR_WENO && NQ == 4; }
+constexpr bool uses_rounds() {
+    return sizeof(T) != 8 && Tl::TS == 15 && (VAR == VAR_WENO || VAR == VAR_UPWIND) && NQ == 4;
+}
 // minimum waves per SIMD of a stage launch (the rounds kernel: seven with
 // direct-to-LDS loads, which hold nothing in registers, at most 72 VGPRs and
 // 23 KB of LDS per workgroup; six, at most 80 VGPRs, when loading through
@@ -1019,8 +1023,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const RunDesc& D,
 }
 
 // ---------------------------------------------------------------------------
-// Fused RK stage in population rounds (D2Q16, WENO-5 standard form, 15 x 16
-// tiles): the same operator, per-face arithmetic and per-cell order of
+// Fused RK stage in population rounds (D2Q16, WENO-5 standard form or an
+// upwind scheme in either theta form, 15 x 16 tiles): the same operator,
+// per-face arithmetic and per-cell order of
 // accumulation as stage_tile, hence the same bits, with less LDS traffic and
 // a quarter of its barriers.
 //
@@ -1046,7 +1051,7 @@ __device__ __forceinline__ T scalar_load(const T* p, int i) {
     return ((const __attribute__((address_space(4))) T*)p)[i];
 }
 
-template <class St, bool LDSDMA, int GN>
+template <class St, int VAR, bool LDSDMA, int GN>
 __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunDesc& D, int t, uint32_t ctr) {
     using Tl = Tile15x16;
     constexpr int NQ = 4, NK = 16;
@@ -1146,6 +1151,7 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
     const int csc = cs < nt ? cs : nt - 1;
     const CellRowK<T> rkr = static_cast<const CellRowK<T>*>(D.rowk)[csc];
     const T epsk = uni<T>(D, U_EPSK);
+    const int scheme = D.scheme;                 // U1 / U2 / U3 (upwind variant)
     const void* rest_t = sizeof(T) == 8 ? static_cast<const void*>(D.rows.rest)
                                         : static_cast<const void*>(D.rest_f);
     const rsrc_t rrest = make_rsrc(rest_t, (uint32_t)(NK * nt * sizeof(T)));
@@ -1265,7 +1271,33 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
         };
         if constexpr (!DMA) read_self();
         // -- theta fluxes: population lp, column l16, interface rows 4w .. 4w+3
-        {
+        if constexpr (VAR == VAR_UPWIND) {
+            // upwind: the three points a, b, c of the flux at interface 4w+f
+            // are rows 4w+f+1 .. 4w+f+3 (positive speed) or 4w+f+4 .. 4w+f+2;
+            // the rest state's part is in the rest table (the flux is linear);
+            // the interface factor is sin(theta) at the interface in the
+            // Komissarov form, 1 otherwise
+            T h[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                if (st > 0 ? (m >= 1 && m <= 6) : (m >= 2 && m <= 7)) {
+                    const T S = sin_row(m);
+                    h[m] = S * tl[(4 * w + m) * PITCH + l16 + NGH];
+                    asm("" : "+v"(h[m]));
+                } else {
+                    h[m] = T(0);
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int ig = s0 + 4 * w + f < nt ? s0 + 4 * w + f : nt;
+                T F = st > 0 ? upwind(scheme, h[f + 1], h[f + 2], h[f + 3])
+                             : upwind(scheme, h[f + 4], h[f + 3], h[f + 2]);
+                F *= scalar_load(&fkt[ig].sI, 0);
+                fth[lp * FTP + (4 * w + f) * TQ + l16] = F;
+            }
+        } else {
+
             // the rest weight of this lane's population (a select, not a
             // per-lane table lookup)
             auto wr_of = [&](int p) { return wrk(ROUND_ORDER[4 * r + p] / NQ, ROUND_ORDER[4 * r + p] % NQ); };
@@ -1308,12 +1340,18 @@ __device__ __forceinline__ void stage_tile_rounds(const StageArgs& A, const RunD
             T g[10];
 #pragma unroll
             for (int m = 0; m < 10; ++m) {
-                const bool need = sp > 0 ? m < 8 || (m < 9 && w == 3) : (m > 0 && (m < 9 || w == 3));
+                const bool need = VAR == VAR_UPWIND
+                                      ? (sp > 0 ? m >= 1 && (m < 7 || (m < 8 && w == 3))
+                                                : m >= 2 && (m < 8 || (m < 9 && w == 3)))
+                                      : (sp > 0 ? m < 8 || (m < 9 && w == 3) : (m > 0 && (m < 9 || w == 3)));
                 g[m] = need ? row[m] : T(0);
             }
             auto face = [&](int f) {
                 T F;
-                if (sp > 0)
+                if constexpr (VAR == VAR_UPWIND)
+                    F = sp > 0 ? upwind(scheme, g[f + 1], g[f + 2], g[f + 3])
+                               : upwind(scheme, g[f + 4], g[f + 3], g[f + 2]);
+                else if (sp > 0)
                     F = weno5x6<T, false>(g[f], g[f + 1], g[f + 2], g[f + 3], g[f + 4], g[f], g[f + 1],
                                           g[f + 2], g[f + 3], g[f + 4], epsk, T(0), T(0), T(0));
                 else
@@ -1409,7 +1447,7 @@ __global__ __launch_bounds__(NTHR, (launch_min_waves<St, Tl, VAR, NQ, LDSDMA>())
     const RunDesc& D = BATCH ? *A.desc[run] : A.run0;
     const uint32_t ctr = sizeof(typename St::T) == 8 ? 0u : *D.ctr;
     if constexpr (uses_rounds<typename St::T, Tl, VAR, NQ>())
-        stage_tile_rounds<St, LDSDMA, GN>(A, D, tg - A.tile_start[run], ctr);
+        stage_tile_rounds<St, VAR, LDSDMA, GN>(A, D, tg - A.tile_start[run], ctr);
     else
         stage_tile<St, Tl, VAR, NQ, GN>(A, D, tg - A.tile_start[run], ctr);
 }
@@ -2284,12 +2322,12 @@ vlbm_status launch_group(vlbm_ctx* const* xs, int m, int stage, hipStream_t stre
     // (single-run MLUPS against the register form: 256 x 512 -3.6 %,
     // 512 x 1024 and 1024 x 2048 equal, 1536 x 3072 +1.1 %, 2048 x 4096 +0.5 %)
     constexpr int DMA_MIN_TILES = 2048;
-    if constexpr (std::is_same<St, StF32>::value && VAR == VAR_WENO) {
-        if (m == 1 && !wide && nb >= DMA_MIN_TILES) {
+    if constexpr (std::is_same<St, StF32>::value && (VAR == VAR_WENO || VAR == VAR_UPWIND)) {
+        if (m == 1 && !wide && !d2q9 && nb >= DMA_MIN_TILES) {
             if (stage == 1)
-                hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR_WENO, 4, true, GN_NONE>), grid, dim3(NTHR), 0, stream, A);
+                hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR, 4, true, GN_NONE>), grid, dim3(NTHR), 0, stream, A);
             else
-                hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR_WENO, 4, true, GN_LOAD>), grid, dim3(NTHR), 0, stream, A);
+                hipLaunchKernelGGL((stage_kernel<St, false, Tile15x16, VAR, 4, true, GN_LOAD>), grid, dim3(NTHR), 0, stream, A);
             return launch_check();
         }
     }

@@ -107,3 +107,37 @@ def test_diagnostics_and_vorticity_do_not_depend_on_the_flux_form():
     kom.close()
     assert np.array_equal(d0, d1)
     assert np.array_equal(o0, o1)
+
+
+def _upwind_bits(nt, nph, storage, scheme, komissarov, tile, steps):
+    from paper_2504_15574_amd import Solver
+    from paper_2504_15574_amd.vlbm import vlbm_set_tile_shape
+    s = Solver(nt, nph, 2e-3, storage=storage, scheme=scheme, komissarov=komissarov)
+    vlbm_set_tile_shape(s.ctx, *tile)
+    s.init_fields(*W.random_state(nt, nph, seed=11, du=0.05, dT=0.05, smooth=False))
+    s.step(steps)
+    f = s.populations()
+    s.close()
+    return f
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("scheme,komissarov", [("u1", False), ("u2", True), ("u3", False), ("u3", True)])
+def test_upwind_rounds_kernel_gives_the_per_population_kernel_bits(storage, scheme, komissarov):
+    # D2Q16 upwind runs on 15 x 16 tiles take the population-rounds kernel, on
+    # 7 x 32 tiles the per-population kernel: same fluxes, same order of
+    # accumulation, same bits (a ragged grid with pole and wrap tiles)
+    print(f"[case] upwind rounds vs per-population {storage} {scheme} kom={komissarov}", flush=True)
+    a = _upwind_bits(61, 96, storage, scheme, komissarov, (15, 16), 6)
+    b = _upwind_bits(61, 96, storage, scheme, komissarov, (7, 32), 6)
+    assert np.isfinite(a).all() and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("komissarov", [False, True])
+def test_upwind_direct_to_lds_form_gives_the_per_population_kernel_bits(komissarov):
+    # 512 x 1024 has 2240 tiles of 15 x 16: a single FP32 run takes the rounds
+    # kernel's direct-to-LDS form
+    print(f"[case] upwind direct-to-LDS vs per-population kom={komissarov}", flush=True)
+    a = _upwind_bits(512, 1024, "f32", "u3", komissarov, (15, 16), 3)
+    b = _upwind_bits(512, 1024, "f32", "u3", komissarov, (7, 32), 3)
+    assert np.isfinite(a).all() and np.array_equal(a, b)
