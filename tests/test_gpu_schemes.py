@@ -141,3 +141,33 @@ def test_upwind_direct_to_lds_form_gives_the_per_population_kernel_bits(komissar
     a = _upwind_bits(512, 1024, "f32", "u3", komissarov, (15, 16), 3)
     b = _upwind_bits(512, 1024, "f32", "u3", komissarov, (7, 32), 3)
     assert np.isfinite(a).all() and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batched_upwind_runs_equal_one_by_one(storage):
+    # upwind runs of two sizes and all three schemes in one batched launch (the
+    # rounds kernel's run lookup) against each run stepped alone
+    print(f"[case] batched upwind {storage}", flush=True)
+    from paper_2504_15574_amd import Ensemble, Solver
+    specs = [(45, 64, "u3", True), (30, 96, "u1", False), (45, 64, "u2", True), (61, 32, "u3", False)]
+
+    def fresh():
+        runs = []
+        for i, (nt, nph, scheme, kom) in enumerate(specs):
+            s = Solver(nt, nph, 2e-3, storage=storage, scheme=scheme, komissarov=kom)
+            s.init_fields(*W.random_state(nt, nph, seed=20 + i, du=0.05, dT=0.05, smooth=False))
+            runs.append(s)
+        return runs
+
+    alone = fresh()
+    for s in alone:
+        s.step(5)
+    together = fresh()
+    ens = Ensemble(together)
+    ens.step(5)
+    for a, b in zip(alone, together):
+        fa, fb = a.populations(), b.populations()
+        assert np.isfinite(fa).all() and np.array_equal(fa, fb)
+    ens.release()
+    for s in alone + together:
+        s.close()
